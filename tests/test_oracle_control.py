@@ -1,0 +1,157 @@
+"""Pins of the oracle's plan (Sec. 5.B) and pruning (Sec. 6), and end-to-end checks.
+
+* Pruning with W in {1, 2} has a closed characterisation that does not follow
+  the greedy loop: the pairs left at W = 2 are those outside the smallest set
+  of largest-D pairs whose removal brings the sum under the budget.
+* Invariants for W in {1, 2, 4}: the budget is met, and undoing the last step
+  breaks it; brute force over all assignments for K/L <= 4 shows the
+  greedy's result is feasible whenever one is.
+* Special cases: S = +inf leaves every pair at native precision and the
+  result is the plain FP64 product; an all-zero block contributes nothing.
+* The distortion controller meets its SNR target on i.i.d. data and its
+  predicted SNR matches the measured one (Sec. 5-6, eq. 20).
+* Border blocks (the cleanup of Sec. 2) give the same accuracy.
+* The single-GEMM workload (256^3, L = 64, W = 2 symmetric, R = 2^20) stays in
+  the exact regime: every unpacked integer equals the brute-force product.
+* Fig. 7 / Sec. 7: with every pair at W = 2 in single precision, symmetric
+  packing is more accurate than asymmetric packing.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import control as ct
+from oracle import packing as pk
+from oracle import pipeline as pl
+from oracle.exactsum import exact_sum
+from tests.oracle_tables import tables
+
+
+def _opt(W, d):
+    return ct.PairOption(W, 0.0, 1.0, 1.0, 0.0, 0.0, 0.0, 0, 1.0, d, 0.0, 0.0)
+
+
+def test_prune_two_levels_closed_form():
+    rng = np.random.default_rng(5)
+    for trial in range(300):
+        n = int(rng.integers(1, 12))
+        d2 = rng.exponential(1.0, n)
+        if trial % 5 == 0:
+            d2[rng.integers(0, n)] = d2[0]            # ties
+        budget = float(rng.uniform(0, d2.sum() * 1.2))
+        opts = [{2: _opt(2, float(d)), 1: _opt(1, 0.0)} for d in d2]
+        got = ct.prune(opts, [2, 1], budget)
+        # closed form: drop the k largest (lowest index first among equals), k minimal
+        order = sorted(range(n), key=lambda l: (-d2[l], l))
+        for k in range(n + 1):
+            keep = set(order[k:])
+            if exact_sum([d2[l] for l in keep]) <= budget:
+                break
+        assert got == [2 if l in keep else 1 for l in range(n)]
+
+
+def test_prune_three_levels_invariants_and_bruteforce():
+    rng = np.random.default_rng(9)
+    for trial in range(200):
+        n = int(rng.integers(1, 5))
+        d2 = rng.exponential(1.0, n)
+        d4 = d2 + rng.exponential(3.0, n)
+        opts = [{4: _opt(4, float(d4[l])), 2: _opt(2, float(d2[l])), 1: _opt(1, 0.0)} for l in range(n)]
+        budget = float(rng.uniform(0, d4.sum()))
+        w = ct.prune(opts, [4, 2, 1], budget)
+        tot = exact_sum([opts[l][w[l]].d for l in range(n)])
+        assert tot <= budget or all(x == 1 for x in w)
+        # some assignment is feasible (all W = 1 has D = 0), so the greedy result must be
+        assert tot <= budget
+        # the step before the last one was infeasible: raising any lowered pair back
+        # by one level either exceeds the budget or was not the greedy's last move
+        feasible = [a for a in itertools.product([4, 2, 1], repeat=n)
+                    if exact_sum([opts[l][a[l]].d for l in range(n)]) <= budget]
+        assert tuple(w) in feasible
+        if all(x == 4 for x in w):
+            assert exact_sum(d4.tolist()) <= budget
+
+
+def test_infinite_snr_is_plain_gemm():
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((128, 192))
+    B = rng.standard_normal((192, 64))
+    cfg = pl.Config(L=64, ctrl="snr", snr_db=float("inf"), w_allowed=(1, 2))
+    res = pl.run(A, B, cfg, calib=tables(64, "sym", "f64", (2,)))
+    assert all(o.W == 1 for o in res.plan.chosen.values())
+    ref = A @ B
+    assert np.linalg.norm(res.C - ref) / np.linalg.norm(ref) < 1e-14
+
+
+def test_zero_block_contributes_nothing():
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((64, 128))
+    A[:, 64:] = 0.0                                   # block (0, 1) of A is all zero
+    B = rng.standard_normal((128, 64))
+    cfg = pl.Config(L=64, ctrl="fixed", fixed_w=2, fixed_rmax=2.0 ** 20)
+    res = pl.run(A, B, cfg, keep=True)
+    o = res.plan.chosen[(0, 0, 1)]
+    assert o.c_a == 0.0 and o.inv == 0.0 and o.d == 0.0
+    assert np.all(res.traces[(0, 0, 1)].r == 0)
+    assert pl.snr_db(res.C, A @ B) > 35.0
+
+
+@pytest.mark.parametrize("dist", ["gaussian", "laplace"])
+@pytest.mark.parametrize("target", [20.0, 30.0, 40.0, 50.0, 60.0])
+def test_snr_control_meets_target(dist, target):
+    A, B = workloads.sweep(dist, n=256, k=512)
+    cfg = pl.Config(L=64, ctrl="snr", snr_db=target, w_allowed=(1, 2, 4))
+    res = pl.run(A, B, cfg, calib=tables(64, "sym", "f64", (2, 4)))
+    got = pl.snr_db(res.C, A @ B)
+    # model prediction: total signal / total expected noise over all outputs
+    sig = sum(ct.signal_term(64, res.plan.stats_a[i][l], res.plan.stats_b[l][j])
+              for (i, j, l) in res.plan.chosen)
+    noise = sum(o.d for o in res.plan.chosen.values())
+    pred = 10 * math.log10(sig / noise) if noise > 0 else float("inf")
+    assert got >= target - 1.0
+    # the model is conservative where the (uniform-input) representation term
+    # enters; with no representation noise it is tight
+    assert got >= pred - 1.0
+    if all(o.s_rep == 0.0 for o in res.plan.chosen.values()):
+        assert abs(got - pred) < 1.0
+
+
+def test_borders_cleanup():
+    rng = np.random.default_rng(8)
+    A = rng.standard_normal((200, 200))
+    B = rng.standard_normal((200, 72))
+    cfg = pl.Config(L=64, ctrl="snr", snr_db=40.0, w_allowed=(1, 2))
+    res = pl.run(A, B, cfg, calib=tables(64, "sym", "f64", (2,)))
+    assert res.C.shape == (200, 72)
+    assert pl.snr_db(res.C, A @ B) >= 39.0
+    o = res.plan.chosen[(3, 1, 3)]                   # last l: L_eff = 200 - 192 = 8
+    assert o.r_safe == 8.0 * o.q_a * o.q_b
+
+
+def test_single_gemm_workload_is_exact():
+    A, B = workloads.single()
+    cfg = pl.Config(L=64, form="sym", prec="f64", ctrl="fixed", fixed_w=2, fixed_rmax=2.0 ** 20)
+    res = pl.run(A, B, cfg, keep=True)
+    assert len(res.traces) == 64
+    for key, tr in res.traces.items():
+        np.testing.assert_array_equal(tr.r.astype(np.int64), tr.r_exact)
+        o = res.plan.chosen[key]
+        assert pk.exact_regime_sym(32, o.q_a, o.q_b, 2, o.p, o.r_safe, "f64")
+    # Prop. 2 prediction of the output SNR (s = 0 here)
+    sig = sum(ct.signal_term(64, res.plan.stats_a[i][l], res.plan.stats_b[l][j]) for (i, j, l) in res.plan.chosen)
+    noise = sum(o.d for o in res.plan.chosen.values())
+    assert abs(pl.snr_db(res.C, A @ B) - 10 * math.log10(sig / noise)) < 0.5
+
+
+def test_symmetric_beats_asymmetric_at_full_w2_single_precision():
+    A, B = workloads.sweep("random_range", n=256)
+    out = {}
+    for form in ("sym", "asym"):
+        cfg = pl.Config(L=64, form=form, prec="f32", ctrl="snr", snr_db=0.0, w_allowed=(1, 2))
+        res = pl.run(A, B, cfg, calib=tables(64, form, "f32", (2,)))
+        assert all(o.W == 2 for o in res.plan.chosen.values())
+        out[form] = pl.snr_db(res.C, A @ B)
+    assert out["sym"] > out["asym"]
