@@ -1,0 +1,201 @@
+/*
+ * tdgemm.h -- throughput-distortion GEMM for AMD MI355X (gfx950).
+ *
+ * C = A B computed by the method of Anastasia & Andreopoulos, "Throughput-
+ * Distortion Computation of Generic Matrix Multiplication": per-block adaptive
+ * companding and rounding of A and B (Sec. 3.A, eq. 3), packing of W rounded
+ * operands into one floating-point word in the symmetric (Sec. 3.B, eqs. 6-7)
+ * or asymmetric (Sec. 3.C, eq. 11) form, the product of the packed L x L
+ * subblocks (eqs. 8, 12), unpacking (eqs. 9-10, 13-14) and reverse companding
+ * (eq. 5), with the companders and packings chosen per subblock pair by the
+ * distortion control of Sec. 5.B and Sec. 6.
+ *
+ * Conventions shared by every entry point:
+ *  - A, B, C and all buffers named "device" are device pointers owned by the
+ *    caller; the library never allocates, frees or retains device memory.
+ *  - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *    Calls enqueue work on it and return without synchronising, except
+ *    tdgemm_plan_export and tdgemm_calibrate, which say so.
+ *  - Matrices are row-major. With trans_a = 0, A is M x K with leading
+ *    dimension lda >= K; with trans_a = 1 the caller stores A^T (K x M,
+ *    lda >= M). Likewise B (K x N, or N x K with trans_b). C is M x N, ldc >= N.
+ *  - Argument and shape errors are detected on the host before anything is
+ *    launched; the call then returns an error status and enqueues nothing.
+ *    HIP launch errors return TDGEMM_E_HIP. Nothing throws across the ABI.
+ *  - Subblock pairs (A_il, B_lj) are numbered pair = (i * nJ + j) * nL + l with
+ *    nI = ceil(M/L), nL = ceil(K/L), nJ = ceil(N/L): inner kernel major, l fastest.
+ *  - Per-pair staging buffers hold one L x L slot of `prec` elements per pair,
+ *    row-major; packed blocks use the leading rows/columns of their slot.
+ */
+#ifndef TDGEMM_H
+#define TDGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TDGEMM_OK = 0,
+  TDGEMM_E_ARG = -1,          /* invalid argument or shape */
+  TDGEMM_E_UNSUPPORTED = -2,  /* valid but not implemented (e.g. W = 3, L = 96) */
+  TDGEMM_E_WORKSPACE = -3,    /* workspace missing or too small */
+  TDGEMM_E_CALIB = -4,        /* calibration table missing or malformed */
+  TDGEMM_E_HIP = -5           /* a HIP runtime call failed */
+} tdgemm_status;
+
+enum { TDGEMM_F64 = 0, TDGEMM_F32 = 1 };                       /* element types */
+enum { TDGEMM_SYM = 1, TDGEMM_ASYM = 2 };                      /* packing forms */
+enum { TDGEMM_CTRL_SNR = 0, TDGEMM_CTRL_FIXED = 1, TDGEMM_CTRL_SEPARABLE = 2 };
+
+typedef struct {
+  int64_t M, N, K;
+  int64_t lda, ldb, ldc;
+  int32_t trans_a, trans_b;   /* 0 or 1, see conventions */
+  int32_t in_dtype;           /* TDGEMM_F64 or TDGEMM_F32: element type of A and B */
+  int32_t prec;               /* TDGEMM_F64 or TDGEMM_F32: arithmetic of the packed path
+                                 (companding, packing, product, unpacking, reverse
+                                 companding) and element type of C. F32 packing of
+                                 F64 inputs is not supported. */
+  int32_t L;                  /* inner-kernel size, eq. (1): 64 or 128 */
+  int32_t form;               /* TDGEMM_SYM or TDGEMM_ASYM */
+  int32_t ctrl;               /* TDGEMM_CTRL_*:
+                                 SNR: Sec. 5.B / Sec. 6 control to snr_db per inner kernel;
+                                 FIXED: every pair at packing fixed_w and range fixed_rmax
+                                        with the eq. (26) companders;
+                                 SEPARABLE: every pair at packing fixed_w with per-block
+                                        companders c = sep_q / max|block| (Sec. 3.A). */
+  uint32_t w_allowed;         /* SNR mode: bit w set => packing W = w allowed; bit 1
+                                 (W = 1, native arithmetic) must be set; W in {1, 2, 4} */
+  int32_t fixed_w;            /* FIXED / SEPARABLE: W in {1, 2, 4} */
+  double snr_db;              /* SNR mode: S_kernel(i, j) in dB for every inner kernel
+                                 (Sec. 6); +inf requests native precision everywhere */
+  double fixed_rmax;          /* FIXED: R_max of eqs. (17), (24) */
+  double sep_q;               /* SEPARABLE: integer range Q >= 1 of the rounded operands */
+  double u_safe;              /* eq. (15) safety term, normally 50 */
+} tdgemm_desc;
+
+/* Representation-noise table s(R_max, W) of Sec. 4.B (eq. 18), device memory:
+ * r[n_r] ascending R values shared by all W; s[3 * n_r] the RMSE in index
+ * units for W = 2 (row 0), 3 (row 1) and 4 (row 2); +inf marks an unusable
+ * point. Read by the plan's kernels only: keep it alive until the stream has
+ * run them. */
+typedef struct {
+  int32_t n_r;
+  const double *r;
+  const double *s;
+} tdgemm_calib;
+
+/* Statistics of one block over its valid elements (Sec. 3, Sec. 5.B):
+ * sigma = sqrt(sumsq / n); sumsq is the sum of squares rounded once. */
+typedef struct {
+  double mn, mx, sumsq;
+  int64_t n;
+} tdgemm_block_stats;
+
+/* One pair's settings (Sec. 5.B option record after the Sec. 6 pruning). */
+typedef struct {
+  double c_a, c_b;            /* companders, eq. (26) (or Q / max|X| when separable) */
+  double inv;                 /* 1 / (c_a c_b), eq. (5) */
+  double d;                   /* expected noise power D_W, eq. (21) */
+  double r_max;               /* R_max* */
+  double s_rep;               /* s(R_max*, W) */
+  double q_a, q_b;            /* [[c max|X|]]: bounds of the rounded operands */
+  int32_t w;                  /* packing W (1 = native floating point) */
+  int32_t p;                  /* z = 2^-p, eq. (15) */
+} tdgemm_pair;
+
+typedef struct tdgemm_plan_s *tdgemm_plan_t;   /* opaque, host memory */
+
+/* Bytes of device workspace tdgemm_plan needs for this descriptor (block
+ * statistics, pair records, inner-kernel budgets). 0 if the descriptor is
+ * invalid. */
+size_t tdgemm_workspace_size(const tdgemm_desc *desc);
+
+/* Sec. 5.B and Sec. 6: per-block statistics of A and B (min, max, sum of
+ * squares), per-pair options for every allowed W (eq. 26 companders at the R_max
+ * minimising the eq. 27 noise over the calibrated grid, z from eq. 15, D_W from
+ * eq. 21) and, per inner kernel, top-down pruning to the SNR budget.
+ * A, B: device inputs (described by desc). calib: required in SNR mode, else
+ * may be NULL. ws: device workspace of ws_bytes >= tdgemm_workspace_size(desc);
+ * it holds the plan and must outlive it. On success *out receives a new plan
+ * (host object, release with tdgemm_plan_destroy). Enqueues the statistics and
+ * plan kernels on stream. */
+tdgemm_status tdgemm_plan(const tdgemm_desc *desc, const void *A, const void *B,
+                          const tdgemm_calib *calib, void *ws, size_t ws_bytes,
+                          void *stream, tdgemm_plan_t *out);
+
+/* Eq. (3): qA[pair] = [[c_a A_il]], qB[pair] = [[c_b B_lj]] per pair (round half
+ * to even, in prec; out-of-range elements 0). W = 1 pairs copy the block
+ * unrounded. qA, qB: device, n_pairs * L * L elements of prec each. */
+tdgemm_status tdgemm_compand(tdgemm_plan_t plan, const void *A, const void *B,
+                             void *qA, void *qB, void *stream);
+
+/* Packing. Symmetric (eqs. 6-7): pA[pair] is L x L/W with W consecutive
+ * columns of qA per word (weights z^i), pB[pair] is L/W x L with W consecutive
+ * rows of qB per word (weights z^-i). Asymmetric (eq. 11): pA[pair] is L/W x L
+ * with W consecutive rows of qA per word (weights z^i); pB[pair] = qB. Words are
+ * evaluated by Horner's rule from the highest slot. W = 1 pairs copy.
+ * Buffers: device, n_pairs * L * L elements of prec each. */
+tdgemm_status tdgemm_pack(tdgemm_plan_t plan, const void *qA, const void *qB,
+                          void *pA, void *pB, void *stream);
+
+/* Packed product (eqs. 8, 12) on the matrix cores, each output accumulated over
+ * the packed index in ascending order.
+ * fused = 0: a = pA, b = pB (as written by tdgemm_pack); out = Rbar, device,
+ *            n_pairs * L * L elements of prec (L x L symmetric, L/W x L asymmetric).
+ * fused = 1: a = A, b = B (as given to tdgemm_plan); out = C. One kernel runs
+ *            every stage per pair -- compand, pack, packed product, unpack,
+ *            reverse companding -- and accumulates C over l ascending. */
+tdgemm_status tdgemm_gemm(tdgemm_plan_t plan, const void *a, const void *b, void *out,
+                          int fused, void *stream);
+
+/* Unpacking (eqs. 9-10 or 13-14) of every pair's Rbar into integers, then
+ * reverse companding (eq. 5) and the l-sum of eq. (2), l ascending:
+ * C_ij = sum_l r_l * inv_l (W = 1 pairs add their native product).
+ * r_int: optional device buffer (NULL to skip) receiving the unpacked integers,
+ * n_pairs * L * L elements of prec. C: device output (overwritten), or NULL
+ * when only r_int is wanted (at least one of the two must be given). */
+tdgemm_status tdgemm_unpack(tdgemm_plan_t plan, const void *Rbar, void *r_int, void *C,
+                            void *stream);
+
+/* Copy the plan's statistics and records to host memory. Any pointer may be
+ * NULL. Sizes: stats_a nI * nL, stats_b nL * nJ, pairs n_pairs, budgets nI * nJ
+ * (D_kernel per inner kernel, SNR mode; 0 otherwise). Synchronises the stream
+ * the plan was made on. */
+tdgemm_status tdgemm_plan_export(tdgemm_plan_t plan, tdgemm_block_stats *stats_a,
+                                 tdgemm_block_stats *stats_b, tdgemm_pair *pairs,
+                                 double *budgets);
+
+/* Grid of the plan: nI, nL, nJ and n_pairs = nI * nL * nJ. */
+tdgemm_status tdgemm_plan_dims(tdgemm_plan_t plan, int64_t *nI, int64_t *nL, int64_t *nJ,
+                               int64_t *n_pairs);
+
+tdgemm_status tdgemm_plan_destroy(tdgemm_plan_t plan);
+
+/* Representation-noise measurement of Sec. 4.B (eq. 18) on the GPU path:
+ * for each integer range q[t] (host, n_q values >= 1) the inputs are integers
+ * uniform on {-q..q}, obtained from the uniform [0, 1) draws u_a, u_b (device,
+ * n_inst * L * L each) as floor(u (2q + 1)) - q; c_A = c_B = 1; R_max = L q^2;
+ * z from eq. (15). The packed product of each instance is unpacked and compared
+ * with the exact product. Outputs (host, n_q each): r_out = R_max, m_out = mean
+ * error, s_out = RMSE (index units; +inf where non-finite). ws: device
+ * workspace of at least tdgemm_calibrate_workspace_size(L, n_inst) bytes.
+ * Synchronises the stream. */
+size_t tdgemm_calibrate_workspace_size(int32_t L, int32_t n_inst);
+tdgemm_status tdgemm_calibrate(int32_t L, int32_t W, int32_t form, int32_t prec,
+                               const double *q, int32_t n_q, const double *u_a,
+                               const double *u_b, int32_t n_inst, double u_safe,
+                               double *r_out, double *m_out, double *s_out, void *ws,
+                               size_t ws_bytes, void *stream);
+
+/* Human-readable name of a status code (static storage). */
+const char *tdgemm_status_string(tdgemm_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDGEMM_H */

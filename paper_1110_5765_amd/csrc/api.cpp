@@ -1,0 +1,354 @@
+// C-ABI of the tdgemm library: argument validation on the host, workspace
+// layout, plan lifecycle and launches. Declarations and contracts: tdgemm.h.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+struct tdgemm_plan_s {
+  tdgemm_desc desc;
+  tdg::Layout ly;
+  char *ws;
+  hipStream_t stream;
+};
+
+namespace {
+
+using tdg::Layout;
+using tdg::Problem;
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+bool valid_w(int w) { return w == 1 || w == 2 || w == 4; }
+
+tdgemm_status validate(const tdgemm_desc *d) {
+  if (!d) return TDGEMM_E_ARG;
+  if (d->M < 0 || d->N < 0 || d->K < 0) return TDGEMM_E_ARG;
+  if (d->trans_a != 0 && d->trans_a != 1) return TDGEMM_E_ARG;
+  if (d->trans_b != 0 && d->trans_b != 1) return TDGEMM_E_ARG;
+  if (d->in_dtype != TDGEMM_F64 && d->in_dtype != TDGEMM_F32) return TDGEMM_E_ARG;
+  if (d->prec != TDGEMM_F64 && d->prec != TDGEMM_F32) return TDGEMM_E_ARG;
+  if (d->prec == TDGEMM_F32 && d->in_dtype == TDGEMM_F64) return TDGEMM_E_UNSUPPORTED;
+  if (d->L != 64 && d->L != 128) return (d->L > 0) ? TDGEMM_E_UNSUPPORTED : TDGEMM_E_ARG;
+  if (d->form != TDGEMM_SYM && d->form != TDGEMM_ASYM) return TDGEMM_E_ARG;
+  const int64_t need_a = d->trans_a ? d->M : d->K;
+  const int64_t need_b = d->trans_b ? d->K : d->N;
+  if (d->lda < (need_a > 0 ? need_a : 1) || d->ldb < (need_b > 0 ? need_b : 1) ||
+      d->ldc < (d->N > 0 ? d->N : 1))
+    return TDGEMM_E_ARG;
+  if (!(d->u_safe > 0.0) || !is_finite(d->u_safe)) return TDGEMM_E_ARG;
+  switch (d->ctrl) {
+    case TDGEMM_CTRL_SNR: {
+      if (std::isnan(d->snr_db)) return TDGEMM_E_ARG;
+      if (!(d->w_allowed & 2u)) return TDGEMM_E_ARG;
+      if (d->w_allowed & 8u) return TDGEMM_E_UNSUPPORTED;      // W = 3 needs L divisible by 3
+      if (d->w_allowed & ~(2u | 4u | 16u | 8u)) return TDGEMM_E_ARG;
+      break;
+    }
+    case TDGEMM_CTRL_FIXED:
+      if (d->fixed_w == 3) return TDGEMM_E_UNSUPPORTED;
+      if (!valid_w(d->fixed_w)) return TDGEMM_E_ARG;
+      if (!(d->fixed_rmax > 0.0) || !is_finite(d->fixed_rmax)) return TDGEMM_E_ARG;
+      break;
+    case TDGEMM_CTRL_SEPARABLE:
+      if (d->fixed_w == 3) return TDGEMM_E_UNSUPPORTED;
+      if (!valid_w(d->fixed_w)) return TDGEMM_E_ARG;
+      if (!(d->sep_q >= 1.0) || !is_finite(d->sep_q)) return TDGEMM_E_ARG;
+      break;
+    default:
+      return TDGEMM_E_ARG;
+  }
+  const int64_t nL = (d->K + d->L - 1) / d->L;
+  if (nL > 512) return TDGEMM_E_UNSUPPORTED;                     // plan kernel keeps 512 per wave
+  return TDGEMM_OK;
+}
+
+Problem problem_of(const tdgemm_desc &d, const Layout &ly) {
+  Problem p;
+  p.M = d.M; p.N = d.N; p.K = d.K;
+  p.lda = d.lda; p.ldb = d.ldb; p.ldc = d.ldc;
+  p.nI = ly.nI; p.nL = ly.nL; p.nJ = ly.nJ;
+  p.L = d.L;
+  return p;
+}
+
+tdg::GemmOperands operands_of(const tdgemm_plan_s *p) {
+  tdg::GemmOperands g;
+  g.pb = problem_of(p->desc, p->ly);
+  g.in_dtype = p->desc.in_dtype;
+  g.prec = p->desc.prec;
+  g.form = p->desc.form;
+  g.ta = p->desc.trans_a != 0;
+  g.tb = p->desc.trans_b != 0;
+  g.pairs = reinterpret_cast<const tdgemm_pair *>(p->ws + p->ly.off_pairs);
+  return g;
+}
+
+tdgemm_status hip_status(hipError_t e) { return e == hipSuccess ? TDGEMM_OK : TDGEMM_E_HIP; }
+
+bool empty_output(const tdgemm_desc &d) { return d.M == 0 || d.N == 0; }
+
+int packing_exponent_host(double r_safe, double u_safe) {
+  int e;
+  double m = std::frexp(2.0 * r_safe + u_safe, &e);
+  return (m == 0.5) ? e - 1 : e;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tdgemm_status_string(tdgemm_status s) {
+  switch (s) {
+    case TDGEMM_OK: return "TDGEMM_OK";
+    case TDGEMM_E_ARG: return "TDGEMM_E_ARG: invalid argument or shape";
+    case TDGEMM_E_UNSUPPORTED: return "TDGEMM_E_UNSUPPORTED: valid but not implemented";
+    case TDGEMM_E_WORKSPACE: return "TDGEMM_E_WORKSPACE: workspace missing or too small";
+    case TDGEMM_E_CALIB: return "TDGEMM_E_CALIB: calibration table missing or malformed";
+    case TDGEMM_E_HIP: return "TDGEMM_E_HIP: HIP runtime error";
+  }
+  return "unknown tdgemm status";
+}
+
+size_t tdgemm_workspace_size(const tdgemm_desc *desc) {
+  if (validate(desc) != TDGEMM_OK) return 0;
+  return tdg::make_layout(desc->M, desc->N, desc->K, desc->L).total;
+}
+
+tdgemm_status tdgemm_plan(const tdgemm_desc *desc, const void *A, const void *B,
+                          const tdgemm_calib *calib, void *ws, size_t ws_bytes, void *stream,
+                          tdgemm_plan_t *out) {
+  if (!out) return TDGEMM_E_ARG;
+  *out = nullptr;
+  tdgemm_status s = validate(desc);
+  if (s != TDGEMM_OK) return s;
+  const Layout ly = tdg::make_layout(desc->M, desc->N, desc->K, desc->L);
+  const bool has_work = !empty_output(*desc) && desc->K > 0;
+  if (has_work && (!A || !B)) return TDGEMM_E_ARG;
+  if (!ws || ws_bytes < ly.total) return TDGEMM_E_WORKSPACE;
+  if (desc->ctrl == TDGEMM_CTRL_SNR) {
+    if (!calib || calib->n_r < 1 || calib->n_r > 512 || !calib->r || !calib->s)
+      return TDGEMM_E_CALIB;
+  }
+  tdgemm_plan_s *p = new (std::nothrow) tdgemm_plan_s;
+  if (!p) return TDGEMM_E_ARG;
+  p->desc = *desc;
+  p->ly = ly;
+  p->ws = static_cast<char *>(ws);
+  p->stream = static_cast<hipStream_t>(stream);
+  if (has_work) {
+    auto *sa = reinterpret_cast<tdgemm_block_stats *>(p->ws + ly.off_stats_a);
+    auto *sb = reinterpret_cast<tdgemm_block_stats *>(p->ws + ly.off_stats_b);
+    hipError_t e = tdg::launch_block_stats(A, desc->in_dtype, desc->M, desc->K, desc->lda,
+                                           desc->trans_a != 0, desc->L, sa, p->stream);
+    if (e == hipSuccess)
+      e = tdg::launch_block_stats(B, desc->in_dtype, desc->K, desc->N, desc->ldb,
+                                  desc->trans_b != 0, desc->L, sb, p->stream);
+    if (e == hipSuccess) {
+      tdg::PlanLaunch pl;
+      pl.pb = problem_of(*desc, ly);
+      pl.stats_a = sa;
+      pl.stats_b = sb;
+      pl.pairs = reinterpret_cast<tdgemm_pair *>(p->ws + ly.off_pairs);
+      pl.budget = reinterpret_cast<double *>(p->ws + ly.off_budget);
+      pl.calib_r = calib ? calib->r : nullptr;
+      pl.calib_s = calib ? calib->s : nullptr;
+      pl.n_r = calib ? calib->n_r : 0;
+      pl.ctrl = desc->ctrl;
+      pl.n_opt = 0;
+      for (int w : {4, 2, 1})
+        if (desc->ctrl != TDGEMM_CTRL_SNR || (desc->w_allowed & (1u << w))) pl.w_desc[pl.n_opt++] = w;
+      if (desc->ctrl != TDGEMM_CTRL_SNR) { pl.n_opt = 1; pl.w_desc[0] = desc->fixed_w; }
+      pl.fixed_w = desc->fixed_w;
+      pl.fixed_rmax = desc->fixed_rmax;
+      pl.sep_q = desc->sep_q;
+      pl.u_safe = desc->u_safe;
+      pl.snr_lin = std::pow(10.0, -desc->snr_db / 10.0);
+      e = tdg::launch_plan(pl, p->stream);
+    }
+    if (e != hipSuccess) {
+      delete p;
+      return TDGEMM_E_HIP;
+    }
+  }
+  *out = p;
+  return TDGEMM_OK;
+}
+
+tdgemm_status tdgemm_plan_dims(tdgemm_plan_t plan, int64_t *nI, int64_t *nL, int64_t *nJ,
+                               int64_t *n_pairs) {
+  if (!plan) return TDGEMM_E_ARG;
+  if (nI) *nI = plan->ly.nI;
+  if (nL) *nL = plan->ly.nL;
+  if (nJ) *nJ = plan->ly.nJ;
+  if (n_pairs) *n_pairs = plan->ly.n_pairs;
+  return TDGEMM_OK;
+}
+
+tdgemm_status tdgemm_plan_destroy(tdgemm_plan_t plan) {
+  if (!plan) return TDGEMM_E_ARG;
+  delete plan;
+  return TDGEMM_OK;
+}
+
+tdgemm_status tdgemm_plan_export(tdgemm_plan_t plan, tdgemm_block_stats *stats_a,
+                                 tdgemm_block_stats *stats_b, tdgemm_pair *pairs,
+                                 double *budgets) {
+  if (!plan) return TDGEMM_E_ARG;
+  if (hipStreamSynchronize(plan->stream) != hipSuccess) return TDGEMM_E_HIP;
+  const Layout &ly = plan->ly;
+  const bool has_work = !empty_output(plan->desc) && plan->desc.K > 0;
+  if (!has_work) return TDGEMM_OK;
+  struct Item { void *dst; size_t off, bytes; } items[] = {
+      {stats_a, ly.off_stats_a, sizeof(tdgemm_block_stats) * ly.nI * ly.nL},
+      {stats_b, ly.off_stats_b, sizeof(tdgemm_block_stats) * ly.nL * ly.nJ},
+      {pairs, ly.off_pairs, sizeof(tdgemm_pair) * ly.n_pairs},
+      {budgets, ly.off_budget, sizeof(double) * ly.nI * ly.nJ}};
+  for (const Item &it : items) {
+    if (!it.dst) continue;
+    if (hipMemcpy(it.dst, plan->ws + it.off, it.bytes, hipMemcpyDeviceToHost) != hipSuccess)
+      return TDGEMM_E_HIP;
+  }
+  return TDGEMM_OK;
+}
+
+tdgemm_status tdgemm_compand(tdgemm_plan_t plan, const void *A, const void *B, void *qA, void *qB,
+                             void *stream) {
+  if (!plan) return TDGEMM_E_ARG;
+  if (plan->ly.n_pairs == 0 || empty_output(plan->desc)) return TDGEMM_OK;
+  if (!A || !B || !qA || !qB) return TDGEMM_E_ARG;
+  return hip_status(tdg::launch_compand(operands_of(plan), A, B, qA, qB, (hipStream_t)stream));
+}
+
+tdgemm_status tdgemm_pack(tdgemm_plan_t plan, const void *qA, const void *qB, void *pA, void *pB,
+                          void *stream) {
+  if (!plan) return TDGEMM_E_ARG;
+  if (plan->ly.n_pairs == 0 || empty_output(plan->desc)) return TDGEMM_OK;
+  if (!qA || !qB || !pA || !pB) return TDGEMM_E_ARG;
+  return hip_status(tdg::launch_pack(operands_of(plan), qA, qB, pA, pB, (hipStream_t)stream));
+}
+
+tdgemm_status tdgemm_gemm(tdgemm_plan_t plan, const void *a, const void *b, void *out, int fused,
+                          void *stream) {
+  if (!plan) return TDGEMM_E_ARG;
+  if (fused != 0 && fused != 1) return TDGEMM_E_ARG;
+  const tdgemm_desc &d = plan->desc;
+  if (empty_output(d)) return TDGEMM_OK;
+  if (!out) return TDGEMM_E_ARG;
+  tdg::GemmOperands g = operands_of(plan);
+  if (d.K == 0) {
+    if (!fused) return TDGEMM_OK;     // no pairs: nothing to multiply
+    return hip_status(tdg::launch_fill_zero(out, d.prec, d.M, d.N, d.ldc, (hipStream_t)stream));
+  }
+  if (!a || !b) return TDGEMM_E_ARG;
+  if (fused) return hip_status(tdg::launch_fused(g, a, b, out, (hipStream_t)stream));
+  return hip_status(tdg::launch_packed_product(g, a, b, out, (hipStream_t)stream));
+}
+
+tdgemm_status tdgemm_unpack(tdgemm_plan_t plan, const void *Rbar, void *r_int, void *C,
+                            void *stream) {
+  if (!plan) return TDGEMM_E_ARG;
+  const tdgemm_desc &d = plan->desc;
+  if (empty_output(d)) return TDGEMM_OK;
+  if (!C && !r_int) return TDGEMM_E_ARG;
+  if (d.K == 0)
+    return C ? hip_status(tdg::launch_fill_zero(C, d.prec, d.M, d.N, d.ldc, (hipStream_t)stream))
+             : TDGEMM_OK;
+  if (!Rbar) return TDGEMM_E_ARG;
+  return hip_status(tdg::launch_unpack(operands_of(plan), Rbar, r_int, C, (hipStream_t)stream));
+}
+
+size_t tdgemm_calibrate_workspace_size(int32_t L, int32_t n_inst) {
+  if ((L != 64 && L != 128) || n_inst < 1) return 0;
+  const size_t slot = tdg::align256(sizeof(double) * (size_t)n_inst * L * L);
+  // qA qB pA pB Rbar r_int refA refB refR, records x2, moments
+  return 9 * slot + 2 * tdg::align256(sizeof(tdgemm_pair) * (size_t)n_inst) + 256;
+}
+
+tdgemm_status tdgemm_calibrate(int32_t L, int32_t W, int32_t form, int32_t prec, const double *q,
+                               int32_t n_q, const double *u_a, const double *u_b, int32_t n_inst,
+                               double u_safe, double *r_out, double *m_out, double *s_out, void *ws,
+                               size_t ws_bytes, void *stream) {
+  if (L != 64 && L != 128) return L > 0 ? TDGEMM_E_UNSUPPORTED : TDGEMM_E_ARG;
+  if (W == 3) return TDGEMM_E_UNSUPPORTED;
+  if (W != 2 && W != 4) return TDGEMM_E_ARG;
+  if (form != TDGEMM_SYM && form != TDGEMM_ASYM) return TDGEMM_E_ARG;
+  if (prec != TDGEMM_F64 && prec != TDGEMM_F32) return TDGEMM_E_ARG;
+  if (!q || n_q < 1 || !u_a || !u_b || n_inst < 1 || !r_out || !m_out || !s_out) return TDGEMM_E_ARG;
+  if (!(u_safe > 0.0) || !is_finite(u_safe)) return TDGEMM_E_ARG;
+  for (int t = 0; t < n_q; ++t)
+    if (!(q[t] >= 1.0) || !is_finite(q[t]) || q[t] != std::floor(q[t])) return TDGEMM_E_ARG;
+  const size_t need = tdgemm_calibrate_workspace_size(L, n_inst);
+  if (!ws || ws_bytes < need) return TDGEMM_E_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char *w = static_cast<char *>(ws);
+  const size_t slot = tdg::align256(sizeof(double) * (size_t)n_inst * L * L);
+  void *qA = w, *qB = w + slot, *pA = w + 2 * slot, *pB = w + 3 * slot, *Rb = w + 4 * slot,
+       *rint_ = w + 5 * slot;
+  double *refA = reinterpret_cast<double *>(w + 6 * slot);
+  double *refB = reinterpret_cast<double *>(w + 7 * slot);
+  double *refR = reinterpret_cast<double *>(w + 8 * slot);
+  const size_t rec = tdg::align256(sizeof(tdgemm_pair) * (size_t)n_inst);
+  auto *pairs_w = reinterpret_cast<tdgemm_pair *>(w + 9 * slot);
+  auto *pairs_1 = reinterpret_cast<tdgemm_pair *>(w + 9 * slot + rec);
+  double *mom = reinterpret_cast<double *>(w + 9 * slot + 2 * rec);
+  const int64_t n = (int64_t)n_inst * L * L;
+
+  tdg::GemmOperands g;
+  g.pb.M = g.pb.N = g.pb.K = L;
+  g.pb.lda = g.pb.ldb = g.pb.ldc = L;
+  g.pb.nI = n_inst; g.pb.nJ = 1; g.pb.nL = 1;
+  g.pb.L = L;
+  g.in_dtype = prec; g.prec = prec; g.form = form; g.ta = g.tb = false;
+  g.pairs = pairs_w;
+  tdg::GemmOperands gref = g;
+  gref.in_dtype = TDGEMM_F64; gref.prec = TDGEMM_F64; gref.form = TDGEMM_SYM;
+  gref.pairs = pairs_1;
+
+  std::vector<tdgemm_pair> hp(n_inst), h1(n_inst);
+  tdgemm_pair one;
+  std::memset(&one, 0, sizeof(one));
+  one.c_a = one.c_b = one.inv = 1.0;
+  one.w = 1;
+  for (auto &x : h1) x = one;
+  if (hipStreamSynchronize(st) != hipSuccess) return TDGEMM_E_HIP;
+  if (hipMemcpy(pairs_1, h1.data(), sizeof(tdgemm_pair) * n_inst, hipMemcpyHostToDevice) != hipSuccess)
+    return TDGEMM_E_HIP;
+  for (int t = 0; t < n_q; ++t) {
+    const double qq = q[t];
+    const double r_max = ((double)L * qq) * qq;
+    tdgemm_pair o = one;
+    o.w = W;
+    o.p = packing_exponent_host(r_max, u_safe);
+    o.r_max = r_max;
+    for (auto &x : hp) x = o;
+    hipError_t e = hipMemcpy(pairs_w, hp.data(), sizeof(tdgemm_pair) * n_inst, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = tdg::launch_int_inputs(u_a, n, qq, prec, qA, st);
+    if (e == hipSuccess) e = tdg::launch_int_inputs(u_b, n, qq, prec, qB, st);
+    if (e == hipSuccess) e = tdg::launch_pack(g, qA, qB, pA, pB, st);
+    if (e == hipSuccess) e = tdg::launch_packed_product(g, pA, pB, Rb, st);
+    if (e == hipSuccess) e = tdg::launch_unpack(g, Rb, rint_, nullptr, st);
+    if (e == hipSuccess) e = tdg::launch_int_inputs(u_a, n, qq, TDGEMM_F64, refA, st);
+    if (e == hipSuccess) e = tdg::launch_int_inputs(u_b, n, qq, TDGEMM_F64, refB, st);
+    if (e == hipSuccess) e = tdg::launch_packed_product(gref, refA, refB, refR, st);
+    if (e == hipSuccess) e = tdg::launch_error_moments(rint_, refR, prec, n, mom, st);
+    double hm[3];
+    if (e == hipSuccess) e = hipMemcpyAsync(hm, mom, sizeof(hm), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return TDGEMM_E_HIP;
+    r_out[t] = r_max;
+    if (hm[2] > 0.0) {
+      m_out[t] = NAN;
+      s_out[t] = INFINITY;
+    } else {
+      m_out[t] = hm[0] / (double)n;
+      s_out[t] = std::sqrt(hm[1] / (double)n);
+    }
+  }
+  return TDGEMM_OK;
+}
+
+}  // extern "C"

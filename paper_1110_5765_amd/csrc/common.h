@@ -1,0 +1,227 @@
+// Shared device helpers of the tdgemm HIP library (gfx950).
+//
+// Compile with -ffp-contract=off: every floating-point expression below is
+// evaluated operation by operation in the order written, with fused
+// multiply-adds only where __builtin_fma is spelled out.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tdgemm.h"
+
+namespace tdg {
+
+constexpr int kThreads = 256;          // threads per workgroup of every kernel
+constexpr int kWave = 64;              // CDNA wavefront width
+constexpr double kDUnavailable = 1e300;  // D of an option the calibration cannot supply
+
+// ---------------------------------------------------------------------------
+// Compensated sums. A running sum is a pair (s, c): s the rounded sum, c the
+// accumulated rounding errors (each obtained exactly by TwoSum). s + c rounded
+// once is the exactly rounded sum except when the exact value lies within about
+// n^2 2^-106 |sum| of a rounding boundary.
+struct CSum {
+  double s, c;
+};
+
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+  s = a + b;
+  double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ CSum csum_add(CSum x, double v) {
+  double s, e;
+  two_sum(x.s, v, s, e);
+  return CSum{s, x.c + e};
+}
+
+__device__ __forceinline__ CSum csum_merge(CSum x, CSum y) {
+  double s, e;
+  two_sum(x.s, y.s, s, e);
+  return CSum{s, (x.c + y.c) + e};
+}
+
+__device__ __forceinline__ double csum_value(CSum x) { return x.s + x.c; }
+
+// Butterfly merge over the 64 lanes, then lane 0's value broadcast so every
+// lane holds the same rounded result.
+__device__ __forceinline__ double wave_csum(CSum x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    CSum y{__shfl_xor(x.s, off), __shfl_xor(x.c, off)};
+    x = csum_merge(x, y);
+  }
+  return __shfl(csum_value(x), 0);
+}
+
+// ---------------------------------------------------------------------------
+// Plan arithmetic: the paper's formulas in the operation order written.
+
+// p = ceil(log2(2 R_safe + u_safe)): z = 2^-p is the largest power of two
+// satisfying eq. (15). Exact: v is an integer below 2^53 and frexp is exact.
+__device__ __forceinline__ int packing_exponent(double r_safe, double u_safe) {
+  double v = 2.0 * r_safe + u_safe;
+  int e;
+  double m = frexp(v, &e);
+  return (m == 0.5) ? e - 1 : e;
+}
+
+struct BlockMoments {
+  double amax;    // max{|min|, max}
+  double sigma;   // sqrt(sumsq / n)
+};
+
+__device__ __forceinline__ BlockMoments moments(const tdgemm_block_stats &st) {
+  BlockMoments b;
+  b.amax = fmax(fabs(st.mn), st.mx);
+  b.sigma = sqrt(st.sumsq / (double)st.n);
+  return b;
+}
+
+// Normalised noise at the eq. (26) companders (eq. 27 read from eqs. 19 and 21):
+// c_tot/(6 s_a s_b) + c_tot^2/(144 s_a^2 s_b^2) + s^2 c_tot^2/(L s_a^2 s_b^2).
+__device__ __forceinline__ double nsr_exact(double L_eff, double amax_a, double amax_b, double ss,
+                                            double r, double s) {
+  double ctot = ((L_eff * amax_a) * amax_b) / r;
+  double t1 = ctot / (6.0 * ss);
+  double t2 = (ctot * ctot) / (144.0 * (ss * ss));
+  double t3 = ((s * s) * (ctot * ctot)) / (L_eff * (ss * ss));
+  return (t1 + t2) + t3;
+}
+
+// Settings of one pair (the fields of tdgemm_pair).
+__device__ __forceinline__ tdgemm_pair option_native() {
+  tdgemm_pair o;
+  o.c_a = 1.0; o.c_b = 1.0; o.inv = 1.0; o.d = 0.0; o.r_max = 0.0; o.s_rep = 0.0;
+  o.q_a = 0.0; o.q_b = 0.0; o.w = 1; o.p = 0;
+  return o;
+}
+
+__device__ __forceinline__ tdgemm_pair option_zero(int W, double u_safe) {
+  tdgemm_pair o;
+  o.c_a = 0.0; o.c_b = 0.0; o.inv = 0.0; o.d = 0.0; o.r_max = 0.0; o.s_rep = 0.0;
+  o.q_a = 0.0; o.q_b = 0.0; o.w = W; o.p = packing_exponent(0.0, u_safe);
+  return o;
+}
+
+// Eq. (21) at companders c_a, c_b: L[(s_a s_nb)^2 + (s_b s_na)^2 + (s_na s_nb)^2]
+// + (s / (c_a c_b))^2 with s_n = 1 / (c sqrt 12).
+__device__ __forceinline__ double noise_eq21(double L_eff, double s_a, double s_b, double c_a,
+                                             double c_b, double s_rep) {
+  const double sqrt12 = 3.4641016151377544;   // correctly rounded sqrt(12)
+  double rep = s_rep / (c_a * c_b);
+  double na = 1.0 / (c_a * sqrt12);
+  double nb = 1.0 / (c_b * sqrt12);
+  double q = L_eff * (((s_a * nb) * (s_a * nb) + (s_b * na) * (s_b * na)) + (na * nb) * (na * nb));
+  return q + rep * rep;
+}
+
+// Eqs. (24), (26), (15), (21) at packing W and range r_max.
+__device__ __forceinline__ tdgemm_pair option_at(int W, double L_eff, const BlockMoments &a,
+                                                 const BlockMoments &b, double r_max, double s_rep,
+                                                 double u_safe) {
+  tdgemm_pair o;
+  double ctot = ((L_eff * a.amax) * b.amax) / r_max;
+  o.c_a = sqrt(b.sigma / (a.sigma * ctot));
+  o.c_b = sqrt(a.sigma / (b.sigma * ctot));
+  o.q_a = rint(o.c_a * a.amax);
+  o.q_b = rint(o.c_b * b.amax);
+  double r_safe = (L_eff * o.q_a) * o.q_b;
+  o.p = packing_exponent(r_safe, u_safe);
+  o.d = noise_eq21(L_eff, a.sigma, b.sigma, o.c_a, o.c_b, s_rep);
+  o.inv = 1.0 / (o.c_a * o.c_b);
+  o.r_max = r_max;
+  o.s_rep = s_rep;
+  o.w = W;
+  return o;
+}
+
+// Per-block companders c = Q / max|X| (same integers for every pair of a block).
+__device__ __forceinline__ tdgemm_pair option_separable(int W, double L_eff, const BlockMoments &a,
+                                                        const BlockMoments &b, double q,
+                                                        double u_safe) {
+  tdgemm_pair o;
+  o.c_a = q / a.amax;
+  o.c_b = q / b.amax;
+  o.q_a = rint(o.c_a * a.amax);
+  o.q_b = rint(o.c_b * b.amax);
+  double r_safe = (L_eff * o.q_a) * o.q_b;
+  o.p = packing_exponent(r_safe, u_safe);
+  o.d = noise_eq21(L_eff, a.sigma, b.sigma, o.c_a, o.c_b, 0.0);
+  o.inv = 1.0 / (o.c_a * o.c_b);
+  o.r_max = r_safe;
+  o.s_rep = 0.0;
+  o.w = W;
+  return o;
+}
+
+// Index of the first minimum of nsr_exact over the table points with finite s,
+// or -1 if there is none. A cheap pass with multiplications finds the
+// approximate minimum; only points within a relative 1e-10 of it (the
+// approximation is accurate to a few ulp) are evaluated with the exact
+// formula, so the result equals a full exact scan.
+__device__ __forceinline__ int argmin_nsr(double L_eff, const BlockMoments &a, const BlockMoments &b,
+                                          const double *r, const double *rinv, const double *s,
+                                          int n_r) {
+  double ss = a.sigma * b.sigma;
+  double x0 = ((L_eff * a.amax) * b.amax) / ss;    // c_tot * R / (s_a s_b)
+  double invL = 1.0 / L_eff;
+  double best = INFINITY;
+  for (int k = 0; k < n_r; ++k) {
+    double sk = s[k];
+    if (!(sk < INFINITY)) continue;
+    double x = x0 * rinv[k];
+    double v = x * (1.0 / 6.0) + (x * x) * ((1.0 / 144.0) + (sk * sk) * invL);
+    best = fmin(best, v);
+  }
+  if (!(best < INFINITY)) return -1;
+  double thr = best * (1.0 + 1e-10);
+  int kbest = -1;
+  double vbest = INFINITY;
+  for (int k = 0; k < n_r; ++k) {
+    double sk = s[k];
+    if (!(sk < INFINITY)) continue;
+    double x = x0 * rinv[k];
+    double v = x * (1.0 / 6.0) + (x * x) * ((1.0 / 144.0) + (sk * sk) * invL);
+    if (v <= thr) {
+      double e = nsr_exact(L_eff, a.amax, b.amax, ss, r[k], sk);
+      if (e < vbest) { vbest = e; kbest = k; }
+    }
+  }
+  return kbest;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout shared by the host code and the kernels.
+struct Layout {
+  int64_t nI, nL, nJ, n_pairs;
+  size_t off_stats_a, off_stats_b, off_pairs, off_budget, total;
+};
+
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+__host__ inline Layout make_layout(int64_t M, int64_t N, int64_t K, int L) {
+  Layout ly;
+  ly.nI = (M + L - 1) / L;
+  ly.nL = (K + L - 1) / L;
+  ly.nJ = (N + L - 1) / L;
+  ly.n_pairs = ly.nI * ly.nL * ly.nJ;
+  size_t off = 0;
+  ly.off_stats_a = off; off = align256(off + sizeof(tdgemm_block_stats) * ly.nI * ly.nL);
+  ly.off_stats_b = off; off = align256(off + sizeof(tdgemm_block_stats) * ly.nL * ly.nJ);
+  ly.off_pairs = off;   off = align256(off + sizeof(tdgemm_pair) * ly.n_pairs);
+  ly.off_budget = off;  off = align256(off + sizeof(double) * ly.nI * ly.nJ);
+  ly.total = off;
+  return ly;
+}
+
+// Problem description as the kernels see it (passed by value).
+struct Problem {
+  int64_t M, N, K, lda, ldb, ldc;
+  int64_t nI, nL, nJ;
+  int L;
+};
+
+}  // namespace tdg

@@ -1,0 +1,59 @@
+// Launch wrappers of the tdgemm kernels (host side, namespace tdg).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace tdg {
+
+struct PlanLaunch {
+  Problem pb;
+  const tdgemm_block_stats *stats_a;
+  const tdgemm_block_stats *stats_b;
+  tdgemm_pair *pairs;
+  double *budget;
+  const double *calib_r;
+  const double *calib_s;
+  int n_r;
+  int ctrl;
+  int n_opt;
+  int w_desc[3];
+  int fixed_w;
+  double fixed_rmax, sep_q, u_safe, snr_lin;
+};
+
+// Operands of the packed path (all device pointers).
+struct GemmOperands {
+  Problem pb;
+  int in_dtype, prec, form;
+  bool ta, tb;
+  const tdgemm_pair *pairs;   // [n_pairs]
+};
+
+hipError_t launch_block_stats(const void *X, int dtype, int64_t rows, int64_t cols, int64_t ld,
+                              bool tr, int L, tdgemm_block_stats *out, hipStream_t st);
+hipError_t launch_plan(const PlanLaunch &p, hipStream_t st);
+
+// staged path
+hipError_t launch_compand(const GemmOperands &g, const void *A, const void *B, void *qA, void *qB,
+                          hipStream_t st);
+hipError_t launch_pack(const GemmOperands &g, const void *qA, const void *qB, void *pA, void *pB,
+                       hipStream_t st);
+hipError_t launch_packed_product(const GemmOperands &g, const void *pA, const void *pB, void *Rbar,
+                                 hipStream_t st);
+hipError_t launch_unpack(const GemmOperands &g, const void *Rbar, void *r_int, void *C,
+                         hipStream_t st);
+
+// fused path
+hipError_t launch_fused(const GemmOperands &g, const void *A, const void *B, void *C, hipStream_t st);
+
+hipError_t launch_fill_zero(void *C, int prec, int64_t M, int64_t N, int64_t ldc, hipStream_t st);
+
+// calibration helpers (integer inputs from uniforms; error moments)
+hipError_t launch_int_inputs(const double *u, int64_t n, double q, int prec, void *out,
+                             hipStream_t st);
+hipError_t launch_error_moments(const void *r, const double *ref, int prec, int64_t n,
+                                double *out2, hipStream_t st);
+
+}  // namespace tdg

@@ -1,0 +1,160 @@
+"""Host-side checks of the C-ABI (no GPU): the library loads, exports every
+function include/tdgemm.h declares, its structs have the layout the binding
+assumes, and invalid descriptors are rejected on the host before any launch."""
+import ctypes
+import math
+import pathlib
+import re
+import subprocess
+
+import pytest
+
+ROOT = pathlib.Path(__file__).resolve().parents[1]
+HEADER = ROOT / "include" / "tdgemm.h"
+
+
+@pytest.fixture(scope="module")
+def lib():
+    so = ROOT / "paper_1110_5765_amd" / "libtdgemm.so"
+    if not so.exists():
+        from paper_1110_5765_amd import build
+        build.build()
+    return ctypes.CDLL(str(so))
+
+
+@pytest.fixture(scope="module")
+def binding(lib):
+    from paper_1110_5765_amd import tdgemm
+    return tdgemm
+
+
+def declared_functions():
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tdgemm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_path():
+    names = declared_functions()
+    for need in ["tdgemm_plan", "tdgemm_compand", "tdgemm_pack", "tdgemm_gemm", "tdgemm_unpack"]:
+        assert need in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    nm = subprocess.run(["nm", "-D", "--defined-only", str(ROOT / "paper_1110_5765_amd" / "libtdgemm.so")],
+                        capture_output=True, text=True, check=True).stdout
+    for n in names:
+        assert re.search(rf"\bT {n}\b", nm), n
+
+
+def test_struct_layout_matches_binding(binding, tmp_path):
+    src = tmp_path / "sizes.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "tdgemm.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+                   'sizeof(tdgemm_desc), sizeof(tdgemm_pair), sizeof(tdgemm_block_stats),'
+                   'sizeof(tdgemm_calib), offsetof(tdgemm_desc, snr_db), offsetof(tdgemm_desc, u_safe),'
+                   'offsetof(tdgemm_pair, w), offsetof(tdgemm_desc, w_allowed));return 0;}\n')
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-std=c99", f"-I{ROOT / 'include'}", str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [ctypes.sizeof(binding.Desc), ctypes.sizeof(binding.Pair), ctypes.sizeof(binding.BlockStats),
+            ctypes.sizeof(binding.Calib), binding.Desc.snr_db.offset, binding.Desc.u_safe.offset,
+            binding.Pair.w.offset, binding.Desc.w_allowed.offset]
+    assert got == want
+    assert binding.PAIR_DTYPE.itemsize == ctypes.sizeof(binding.Pair)
+    assert binding.STATS_DTYPE.itemsize == ctypes.sizeof(binding.BlockStats)
+
+
+def _desc(binding, **kw):
+    d = binding.Desc()
+    d.M, d.N, d.K = 256, 256, 256
+    d.lda = d.ldb = d.ldc = 256
+    d.in_dtype = d.prec = binding.F64
+    d.L = 64
+    d.form = binding.SYM
+    d.ctrl = binding.CTRL_SNR
+    d.w_allowed = binding.w_mask((1, 2, 4))
+    d.fixed_w = 2
+    d.snr_db = 40.0
+    d.fixed_rmax = 2.0 ** 20
+    d.sep_q = 127.0
+    d.u_safe = 50.0
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("kw,status", [
+    ({}, 0),
+    ({"L": 96}, -2), ({"L": 0}, -1), ({"form": 3}, -1), ({"prec": 7}, -1),
+    ({"in_dtype": 0, "prec": 1}, -2), ({"M": -1}, -1), ({"lda": 100}, -1), ({"ldc": 10}, -1),
+    ({"trans_a": 2}, -1), ({"w_allowed": 4}, -1), ({"w_allowed": 2 | 8}, -2),
+    ({"w_allowed": 2 | 32}, -1), ({"ctrl": 9}, -1), ({"snr_db": math.nan}, -1),
+    ({"ctrl": 1, "fixed_w": 3}, -2), ({"ctrl": 1, "fixed_w": 5}, -1), ({"ctrl": 1, "fixed_rmax": 0.0}, -1),
+    ({"ctrl": 2, "sep_q": 0.5}, -1), ({"u_safe": 0.0}, -1), ({"K": 64 * 513, "lda": 64 * 513}, -2),
+])
+def test_descriptor_validation(binding, lib, kw, status):
+    d = _desc(binding, **kw)
+    size = lib.tdgemm_workspace_size
+    size.restype = ctypes.c_size_t
+    n = size(ctypes.byref(d))
+    assert (n > 0) == (status == 0)
+    h = ctypes.c_void_p()
+    # invalid descriptors are rejected before anything touches the GPU
+    if status != 0:
+        st = lib.tdgemm_plan(ctypes.byref(d), None, None, None, None, ctypes.c_size_t(0), None, ctypes.byref(h))
+        assert st == status
+        assert not h.value
+
+
+def test_plan_rejects_missing_workspace_and_calibration(binding, lib):
+    d = _desc(binding)
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(0x1000)   # never dereferenced: the checks fail first
+    st = lib.tdgemm_plan(ctypes.byref(d), dummy, dummy, None, None, ctypes.c_size_t(0), None, ctypes.byref(h))
+    assert st == -3
+    need = binding.tdgemm_workspace_size(d)
+    st = lib.tdgemm_plan(ctypes.byref(d), dummy, dummy, None, dummy, ctypes.c_size_t(need - 1), None, ctypes.byref(h))
+    assert st == -3
+    st = lib.tdgemm_plan(ctypes.byref(d), dummy, dummy, None, dummy, ctypes.c_size_t(need), None, ctypes.byref(h))
+    assert st == -4                    # SNR control without a calibration table
+    bad = binding.Calib(0, 0x1000, 0x1000)
+    st = lib.tdgemm_plan(ctypes.byref(d), dummy, dummy, ctypes.byref(bad), dummy, ctypes.c_size_t(need), None,
+                         ctypes.byref(h))
+    assert st == -4
+
+
+def test_calibrate_argument_errors(binding, lib):
+    lib.tdgemm_calibrate_workspace_size.restype = ctypes.c_size_t
+    assert lib.tdgemm_calibrate_workspace_size(96, 5) == 0
+    assert lib.tdgemm_calibrate_workspace_size(64, 5) > 0
+    f = lib.tdgemm_calibrate
+    z = ctypes.c_void_p(0x1000)
+    q = (ctypes.c_double * 1)(0.5)    # q < 1 is rejected
+    out = (ctypes.c_double * 1)()
+    assert f(64, 2, 1, 0, q, 1, z, z, 5, ctypes.c_double(50.0), out, out, out, z, ctypes.c_size_t(1 << 30), None) == -1
+    q[0] = 4.0
+    assert f(64, 3, 1, 0, q, 1, z, z, 5, ctypes.c_double(50.0), out, out, out, z, ctypes.c_size_t(1 << 30), None) == -2
+    assert f(64, 2, 1, 0, q, 1, z, z, 5, ctypes.c_double(50.0), out, out, out, z, ctypes.c_size_t(16), None) == -3
+
+
+def test_status_strings(lib):
+    f = lib.tdgemm_status_string
+    f.restype = ctypes.c_char_p
+    for s in (0, -1, -2, -3, -4, -5):
+        assert f(s).decode().startswith("TDGEMM_")
+
+
+def test_matrix_layout_detection(binding):
+    import torch
+    X = torch.zeros(5, 7)
+    assert binding.matrix_layout(X) == (0, 7)
+    assert binding.matrix_layout(X.t()) == (1, 7)
+    Y = torch.zeros(6, 10)[:, :4]
+    assert binding.matrix_layout(Y) == (0, 10)
+    with pytest.raises(ValueError):
+        binding.matrix_layout(torch.zeros(4, 6)[:, ::2])

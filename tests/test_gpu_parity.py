@@ -1,0 +1,176 @@
+"""GPU parity: the HIP path, called through the C-ABI, against the CPU oracle.
+
+Bar (integer and byte work bit-exact; floating point within the stated bound):
+* block statistics, pair records (W, p, companders, D, R, s) and budgets: bit-exact;
+* companded integers, packed words, packed products and unpacked integers:
+  bit-exact (the packed products are FMA chains in ascending packed index on
+  both sides: the matrix cores accumulate exactly that way);
+* C: relative Frobenius error <= 1e-12 (FP64 packing) or 1e-5 (FP32 packing),
+  and the fused kernel equal to the staged path bit for bit.
+Shapes span several tiles and ragged tails on every axis; both packing forms,
+both block sizes, all three control modes, transposed operands and the empty
+and single-row cases are covered.
+"""
+import math
+import zlib
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import pipeline as pl
+from tests.gpu_common import compare_plan, device_calib, log, oracle_cfg, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def td():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1110_5765_amd import tdgemm
+    return tdgemm
+
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+CASES = [
+    # name, M, K, N, L, form, in, prec, ctrl, snr, w_allowed, fixed_w, ta, tb
+    ("single_sym_fixed", 256, 256, 256, 64, "sym", "f64", "f64", "fixed", 0.0, (1, 2), 2, 0, 0),
+    ("ragged_sym_snr40", 200, 330, 150, 64, "sym", "f64", "f64", "snr", 40.0, (1, 2, 4), 2, 0, 0),
+    ("ragged_asym_snr40", 200, 330, 150, 64, "asym", "f64", "f64", "snr", 40.0, (1, 2, 4), 2, 0, 0),
+    ("sym_snr20_w4", 192, 256, 128, 64, "sym", "f64", "f64", "snr", 20.0, (1, 2, 4), 2, 0, 0),
+    ("asym_snr20_w4", 192, 256, 128, 64, "asym", "f64", "f64", "snr", 20.0, (1, 2, 4), 2, 0, 0),
+    ("sym_snr60", 128, 384, 128, 64, "sym", "f64", "f64", "snr", 60.0, (1, 2), 2, 0, 0),
+    ("sym_inf_native", 130, 200, 70, 64, "sym", "f64", "f64", "snr", math.inf, (1, 2), 2, 0, 0),
+    ("L128_sym", 300, 400, 260, 128, "sym", "f64", "f64", "snr", 40.0, (1, 2, 4), 2, 0, 0),
+    ("L128_asym", 300, 400, 260, 128, "asym", "f64", "f64", "snr", 40.0, (1, 2, 4), 2, 0, 0),
+    ("L128_asym_w4", 256, 256, 256, 128, "asym", "f64", "f64", "fixed", 0.0, (1, 4), 4, 0, 0),
+    ("trans_a", 150, 200, 90, 64, "sym", "f64", "f64", "snr", 40.0, (1, 2), 2, 1, 0),
+    ("trans_b", 150, 200, 90, 64, "asym", "f64", "f64", "snr", 40.0, (1, 2), 2, 0, 1),
+    ("trans_ab_L128", 150, 200, 90, 128, "sym", "f64", "f64", "snr", 40.0, (1, 2), 2, 1, 1),
+    ("f32_in_f64_pack", 200, 300, 100, 64, "sym", "f32", "f64", "snr", 40.0, (1, 2), 2, 0, 0),
+    ("f32_pack_sym", 200, 300, 100, 64, "sym", "f32", "f32", "snr", 15.0, (1, 2), 2, 0, 0),
+    ("f32_pack_asym_L128", 200, 300, 160, 128, "asym", "f32", "f32", "snr", 10.0, (1, 2), 2, 0, 0),
+    ("separable_q127", 256, 256, 192, 128, "sym", "f64", "f64", "separable", 0.0, (1, 2), 2, 0, 0),
+    ("single_row", 1, 100, 70, 64, "sym", "f64", "f64", "snr", 40.0, (1, 2), 2, 0, 0),
+    ("k_below_L", 70, 20, 90, 64, "asym", "f64", "f64", "snr", 30.0, (1, 2, 4), 2, 0, 0),
+]
+
+
+def _inputs(M, K, N, dt, ta, tb, seed):
+    r = np.random.default_rng(seed)
+    A = r.standard_normal((M, K)) * (1.0 + 9.0 * r.random((M, 1)))      # uneven row scales
+    B = r.laplace(0.0, 1.0, (K, N))
+    if M >= 64 and K >= 64:
+        A[:64, :64] = 0.0                                                 # an all-zero block
+    A = A.astype(dt)
+    B = B.astype(dt)
+    At = to_dev(A.T.copy()).t() if ta else to_dev(A)
+    Bt = to_dev(B.T.copy()).t() if tb else to_dev(B)
+    return A, B, At, Bt
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_stagewise_parity(td, case):
+    name, M, K, N, L, form, ind, prec, ctrl, snr, wal, fw, ta, tb = case
+    log(f"[parity] {name}: M={M} K={K} N={N} L={L} {form} in={ind} prec={prec} ctrl={ctrl} snr={snr}")
+    dt = np.float64 if ind == "f64" else np.float32
+    A, B, Ad, Bd = _inputs(M, K, N, dt, ta, tb, seed=zlib.crc32(name.encode()))
+    rmax = float(2 ** 20) if L == 64 else float(2 ** 21)
+    calib, tabs = device_calib(td, L, form, prec, tuple(w for w in wal if w > 1) or (2,))
+    cfg = oracle_cfg(L, form, prec, ctrl, snr, wal, fw, rmax, 127.0)
+    res = pl.run(A, B, cfg, calib=tabs, keep=True)
+
+    desc = td.make_desc(Ad, Bd, L=L, form=form, prec=prec, ctrl=ctrl, snr_db=snr, w_allowed=wal,
+                        fixed_w=fw, fixed_rmax=rmax, sep_q=127.0)
+    plan = td.tdgemm_plan(desc, Ad, Bd, calib if ctrl == "snr" else None)
+    sa, sb, pairs, budget = td.tdgemm_plan_export(plan)
+    nI, nL, nJ, npairs = plan.dims
+    tiles = [(i, j) for i in range(nI) for j in range(nJ)]
+    compare_plan(pairs, budget, sa, sb, res, tiles)
+
+    pt = td.torch_dtype(desc.prec)
+    n = td.slot_elems(plan)
+    bufs = {k: torch.full((n,), float("nan"), dtype=pt, device="cuda") for k in
+            ("qA", "qB", "pA", "pB", "R", "r")}
+    C_st = torch.full((M, N), float("nan"), dtype=pt, device="cuda")
+    C_fu = torch.full((M, N), float("nan"), dtype=pt, device="cuda")
+    td.tdgemm_compand(plan, Ad, Bd, bufs["qA"], bufs["qB"])
+    td.tdgemm_pack(plan, bufs["qA"], bufs["qB"], bufs["pA"], bufs["pB"])
+    td.tdgemm_gemm(plan, bufs["pA"], bufs["pB"], bufs["R"], fused=0)
+    td.tdgemm_unpack(plan, bufs["R"], bufs["r"], C_st)
+    td.tdgemm_gemm(plan, Ad, Bd, C_fu, fused=1)
+    torch.cuda.synchronize()
+    h = {k: v.cpu().numpy().reshape(npairs, L, L) for k, v in bufs.items()}
+
+    for i in range(nI):
+        for j in range(nJ):
+            for l in range(nL):
+                p = (i * nJ + j) * nL + l
+                tr = res.traces[(i, j, l)]
+                W = int(pairs[i, j, l]["w"])
+                sym = form == "sym" or W == 1
+                np.testing.assert_array_equal(h["qA"][p], tr.qa, err_msg=f"qA {p}")
+                np.testing.assert_array_equal(h["qB"][p], tr.qb, err_msg=f"qB {p}")
+                pa = h["pA"][p].ravel()[:tr.abar.size].reshape(tr.abar.shape)
+                pb = h["pB"][p].ravel()[:tr.bbar.size].reshape(tr.bbar.shape)
+                np.testing.assert_array_equal(pa, tr.abar, err_msg=f"pA {p}")
+                np.testing.assert_array_equal(pb, tr.bbar, err_msg=f"pB {p}")
+                rows = L if sym else L // W
+                np.testing.assert_array_equal(h["R"][p][:rows], tr.rbar, err_msg=f"Rbar {p}")
+                np.testing.assert_array_equal(h["r"][p], tr.r, err_msg=f"r {p}")
+    Cs = C_st.cpu().numpy()
+    Cf = C_fu.cpu().numpy()
+    assert np.all(np.isfinite(Cs)) and np.all(np.isfinite(Cf))
+    np.testing.assert_array_equal(Cf, Cs)                 # fused == staged, bit for bit
+    assert rel_err(Cs, res.C) <= TOL[prec]
+    exact_c = np.array_equal(Cs, res.C)
+    ref = A.astype(np.float64) @ B.astype(np.float64)
+    log(f"[parity] {name}: C rel err {rel_err(Cs, res.C):.3e} (bit-exact: {exact_c}), "
+        f"SNR vs FP64 {pl.snr_db(Cs, ref):.2f} dB, W hist "
+        f"{ {w: int((pairs['w'] == w).sum()) for w in (1, 2, 4)} }")
+
+
+def test_fused_deterministic(td):
+    A, B = workloads.sweep("laplace", n=512)
+    Ad, Bd = to_dev(A), to_dev(B)
+    calib, _ = device_calib(td, 64, "sym", "f64")
+    outs = []
+    for _ in range(3):
+        C, _ = td.matmul(Ad, Bd, calib, L=64, form="sym", ctrl="snr", snr_db=40.0, w_allowed=(1, 2, 4))
+        outs.append(C.cpu().numpy())
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
+
+
+@pytest.mark.parametrize("M,K,N", [(0, 64, 64), (64, 0, 64), (64, 64, 0), (0, 0, 0)])
+def test_empty_shapes(td, M, K, N):
+    Ad = torch.randn(M, K, dtype=torch.float64, device="cuda")
+    Bd = torch.randn(K, N, dtype=torch.float64, device="cuda")
+    calib, _ = device_calib(td, 64, "sym", "f64")
+    C = torch.full((M, N), float("nan"), dtype=torch.float64, device="cuda")
+    td.matmul(Ad, Bd, calib, out=C, L=64)
+    torch.cuda.synchronize()
+    assert torch.all(C == 0)                              # K = 0 gives zeros; others are empty
+
+
+@pytest.mark.parametrize("form,prec,W,L", [("sym", "f64", 2, 64), ("asym", "f64", 2, 64),
+                                           ("sym", "f64", 4, 64), ("sym", "f32", 2, 64),
+                                           ("asym", "f64", 2, 128)])
+def test_calibration_parity(td, form, prec, W, L):
+    """Sec. 4.B measurement on the GPU path equals the oracle's on the same draws."""
+    from oracle import calibration as cal
+    ua, ub = workloads.calib_uniforms(L)
+    qs = [q for q in cal.q_grid(1 << 18 if prec == "f64" else 1 << 10)][::3]
+    r, m, s = td.tdgemm_calibrate(L, W, form, prec, qs, to_dev(ua), to_dev(ub))
+    for t, q in enumerate(qs):
+        R, mo, so = cal.measure(L, W, form, prec, q, ua, ub)
+        assert r[t] == R
+        if math.isinf(so):
+            assert math.isinf(s[t])
+        else:
+            assert s[t] == so and m[t] == mo, (q, s[t], so, m[t], mo)
+    log(f"[calib] {form} {prec} W={W} L={L}: {len(qs)} points equal; first nonzero s at R="
+        f"{next((x for x, y in zip(r, s) if y > 0), None)}")
