@@ -157,36 +157,37 @@ __device__ __forceinline__ tdgemm_pair option_separable(int W, double L_eff, con
   return o;
 }
 
-// Index of the first minimum of nsr_exact over the table points with finite s,
-// or -1 if there is none. A cheap pass with multiplications finds the
-// approximate minimum; only points within a relative 1e-10 of it (the
-// approximation is accurate to a few ulp) are evaluated with the exact
-// formula, so the result equals a full exact scan.
+// Index (into the full table) of the first minimum of nsr_exact over the
+// table points with finite s, or -1 if there is none.
+//
+// Only non-dominated points are scanned: a point k is dominated when a point
+// k' with a larger R has s[k'] / R[k'] <= s[k] / R[k]; then every term of the
+// noise is smaller at k' (the first two strictly, by the grid spacing), so k
+// can never be the first minimum. `idx` lists the remaining points in
+// ascending R; `fr` and `fs2` hold 1/R and s^2 in FP32. An FP32 pass finds the
+// approximate minimum (relative error below 1e-6); the exact formula is then
+// evaluated, in ascending order, at every point within a relative 1e-5 of it,
+// so the result equals a full exact scan.
 __device__ __forceinline__ int argmin_nsr(double L_eff, const BlockMoments &a, const BlockMoments &b,
-                                          const double *r, const double *rinv, const double *s,
-                                          int n_r) {
-  double ss = a.sigma * b.sigma;
-  double x0 = ((L_eff * a.amax) * b.amax) / ss;    // c_tot * R / (s_a s_b)
-  double invL = 1.0 / L_eff;
-  double best = INFINITY;
-  for (int k = 0; k < n_r; ++k) {
-    double sk = s[k];
-    if (!(sk < INFINITY)) continue;
-    double x = x0 * rinv[k];
-    double v = x * (1.0 / 6.0) + (x * x) * ((1.0 / 144.0) + (sk * sk) * invL);
-    best = fmin(best, v);
+                                          const double *r, const double *s, const short *idx,
+                                          const float *fr, const float *fs2, int cnt) {
+  const double ss = a.sigma * b.sigma;
+  const float x0 = (float)(((L_eff * a.amax) * b.amax) / ss);   // c_tot * R / (s_a s_b)
+  const float invL = 1.0f / (float)L_eff;
+  float best = INFINITY;
+  for (int i = 0; i < cnt; ++i) {
+    const float x = x0 * fr[i];
+    best = fminf(best, x * ((1.0f / 6.0f) + x * ((1.0f / 144.0f) + fs2[i] * invL)));
   }
-  if (!(best < INFINITY)) return -1;
-  double thr = best * (1.0 + 1e-10);
+  const float thr = (best < INFINITY) ? best * (1.0f + 1e-5f) : INFINITY;
   int kbest = -1;
   double vbest = INFINITY;
-  for (int k = 0; k < n_r; ++k) {
-    double sk = s[k];
-    if (!(sk < INFINITY)) continue;
-    double x = x0 * rinv[k];
-    double v = x * (1.0 / 6.0) + (x * x) * ((1.0 / 144.0) + (sk * sk) * invL);
+  for (int i = 0; i < cnt; ++i) {
+    const float x = x0 * fr[i];
+    const float v = x * ((1.0f / 6.0f) + x * ((1.0f / 144.0f) + fs2[i] * invL));
     if (v <= thr) {
-      double e = nsr_exact(L_eff, a.amax, b.amax, ss, r[k], sk);
+      const int k = idx[i];
+      const double e = nsr_exact(L_eff, a.amax, b.amax, ss, r[k], s[k]);
       if (e < vbest) { vbest = e; kbest = k; }
     }
   }

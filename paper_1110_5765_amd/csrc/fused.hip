@@ -1,22 +1,30 @@
 // Fused throughput-distortion GEMM: every stage of a subblock pair in one
 // kernel (Sec. 3 with the settings of Sec. 5.B / Sec. 6).
 //
-// One workgroup (L / 16 wavefronts) computes one L x L inner kernel R_ij and walks
-// its pairs l = 0, 1, ... in order. Each pair's K extent is cut into chunks of
-// 16 raw columns. For every chunk the threads load raw A / B values from HBM,
-// compand them (eq. 3) and pack them (eqs. 6-7, or 11) straight into a
-// double-buffered LDS tile; wave w then runs FP64 (or FP32) 16x16x4 MFMAs for
-// output columns 16w..16w+15, accumulating the packed product over the
-// packed index in ascending order. After a pair's last chunk the packed result
-// is unpacked in registers (eqs. 9-10 or 13-14), reverse-companded (eq. 5) and
-// added to a register-resident C tile (eq. 2). W = 1 pairs run the plain
-// product. C is written once at the end.
+// One workgroup (L / 16 wavefronts) computes one L x L inner kernel R_ij and
+// walks its pairs l = 0, 1, ... in order. Each pair's K extent is cut into
+// chunks of 32 raw columns. For every chunk the threads load raw A / B values
+// from HBM (the next chunk's loads are in flight while the current one is
+// multiplied), compand them (eq. 3) and pack them (eqs. 6-7, or 11) straight
+// into a double-buffered LDS tile; each wavefront then runs FP64 (or FP32)
+// 16x16x4 MFMAs for its 64-row x (L/4)-column part of the tile, accumulating
+// the packed product over the packed index in ascending order. After a pair's last chunk the packed
+// result is unpacked in registers (eqs. 9-10 or 13-14), reverse-companded
+// (eq. 5) and added to a register-resident C tile (eq. 2). W = 1 pairs run the
+// plain product. C is written once at the end.
 //
-// Row placement: lane (g = lane / 16, c = lane % 16) keeps, for row block rb
-// and register r, the C element of tile row 16 rb + 4 g + r. The LDS row of the
+// Row placement: lane (g = lane / 16, c = lane % 16) of the wavefront owning
+// rows 64 wr.. keeps, for its row block rb and register r, the C element of tile
+// row 64 wr + 16 rb + 4 g + r. The LDS row of the
 // A operand that feeds that result slot is permuted accordingly, which for the
 // asymmetric form also routes the W rows unpacked from one packed word to the
 // same lane whatever the pair's W.
+//
+// Thread layout of the raw loads (NT = 4 L threads, 8 values per thread and
+// operand per chunk), independent of W so that prefetching may cross pairs:
+//   A, symmetric form:  one row, 8 consecutive columns (packs along columns);
+//   A, asymmetric form: one column, 8 consecutive rows (packs along rows);
+//   B:                  one column, 8 consecutive rows.
 #include <type_traits>
 
 #include "common.h"
@@ -24,6 +32,14 @@
 #include "mfma.h"
 
 namespace tdg {
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>());
+    static_for<I + 1, N>(f);
+  }
+}
 
 // position (0..15) of the A-operand row that produces lane group g, register r
 template <typename PT> __device__ __forceinline__ int mfma_pos(int g, int r);
@@ -45,222 +61,210 @@ __device__ __forceinline__ int lds_row_of(int m, int W) {
   return (m & ~15) + mfma_pos<PT>(g, r);
 }
 
-template <typename PT>
-__device__ __forceinline__ PT compand_v(PT x, PT c, int W) {
-  return (W == 1) ? x : rint(c * x);
-}
-
 template <typename IT, typename PT, int L, int FORM, bool TA, bool TB>
-__global__ __launch_bounds__(4 * L) void k_fused(GemmOperands g, const IT *__restrict__ A,
-                                                    const IT *__restrict__ B, PT *__restrict__ C,
-                                                    int64_t ntiles, int64_t per_xcd) {
-  constexpr int NT = 4 * L;           // threads: L / 16 wavefronts, one 16-column strip each
-  constexpr int RB = L / 16;          // 16-row blocks of the tile
-  constexpr int CB = 1;               // 16-column blocks per wave
-  constexpr int V = 16 * L / NT;      // raw values per thread per operand per chunk (4)
-  constexpr int SA = 17;              // LDS row stride of the A chunk (odd: no bank conflicts)
-  constexpr int SB = L + 1;
-  constexpr int NCH = L / 16;         // chunks per pair
+struct Fused {
+  static constexpr int TN = 64;           // output columns per workgroup
+  static constexpr int NT = 4 * L;        // threads: L / 16 wavefronts as (L / 64) x 4
+  static constexpr int WC = 4;            // wavefront columns, 16 output columns each
+  static constexpr int RB = 4;            // 16-row blocks per wavefront (64 rows)
+  static constexpr int CB = 1;            // 16-column blocks per wavefront
+  static constexpr int KC = (L == 64) ? 16 : 32;  // raw inner columns per chunk
+  static constexpr int VA = KC * L / NT;  // raw A values per thread per chunk (8)
+  static constexpr int VB = KC * TN / NT; // raw B values per thread per chunk (8 or 4)
+  // LDS row strides in elements: with an odd A stride the 16 rows read by one
+  // group of 16 lanes fall on distinct bank pairs.
+  static constexpr int SA = KC + 1;
+  static constexpr int SB = TN + 1;
+  static constexpr int NCH = L / KC;      // chunks per pair
+  static constexpr int PF = 2;            // register sets of raw loads (chunks g+1, g+2)
   typedef typename Mfma<PT>::Acc Acc;
-  __shared__ PT sA[2][L * SA];
-  __shared__ PT sB[2][16 * SB];
 
-  // XCD-aware tile order: workgroups are dealt to the 8 XCDs round-robin, so
-  // give each XCD a contiguous range, grouped 8 tile-rows at a time (shared
-  // B panels, then A panels, stay in that XCD's L2).
-  const int64_t bid = blockIdx.x;
-  const int64_t lin = (bid & 7) * per_xcd + (bid >> 3);
-  if (lin >= ntiles) return;
-  const Problem &pb = g.pb;
-  constexpr int64_t GROUP = 8;
-  const int64_t grp = lin / (GROUP * pb.nJ);
-  const int64_t first_i = grp * GROUP;
-  const int64_t gsize = min(GROUP, pb.nI - first_i);
-  const int64_t in_grp = lin - grp * GROUP * pb.nJ;
-  const int64_t ti = first_i + in_grp % gsize;
-  const int64_t tj = in_grp / gsize;
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int lg = lane >> 4, lc = lane & 15;
-  const int wcol = wave * 16;
-  const int64_t r0 = ti * L, c0 = tj * L;
-  const tdgemm_pair *prs = g.pairs + (ti * pb.nJ + tj) * pb.nL;
-
-  Acc accR[RB][CB], accC[RB][CB];
-#pragma unroll
-  for (int a = 0; a < RB; ++a)
-#pragma unroll
-    for (int b = 0; b < CB; ++b) { accR[a][b] = Mfma<PT>::zero(); accC[a][b] = Mfma<PT>::zero(); }
-
-  PT ra[V], rb[V];
-
-  // --- raw loads of chunk (l, kc) ---------------------------------------
-  auto load_chunk = [&](int64_t l, int kc, int W) {
-    const int64_t k0 = l * L + kc * 16;
-    const bool colseg = (FORM == TDGEMM_ASYM) && W > 1;
-    if (!colseg) {                        // thread: one row m, V consecutive k
-      if (!TA) {
-        const int m = tid / (16 / V), ks0 = (tid % (16 / V)) * V;
-        const int64_t row = r0 + m;
-#pragma unroll
-        for (int q = 0; q < V; ++q) {
-          const int64_t col = k0 + ks0 + q;
-          ra[q] = (row < pb.M && col < pb.K) ? (PT)A[row * pb.lda + col] : (PT)0;
-        }
-      } else {
-        const int m = tid % L, ks0 = (tid / L) * V;
-        const int64_t row = r0 + m;
-#pragma unroll
-        for (int q = 0; q < V; ++q) {
-          const int64_t col = k0 + ks0 + q;
-          ra[q] = (row < pb.M && col < pb.K) ? (PT)A[col * pb.lda + row] : (PT)0;
-        }
-      }
-    } else {                              // thread: one column k, V consecutive rows
-      if (!TA) {
-        const int k = tid % 16, ms0 = (tid / 16) * V;
-        const int64_t col = k0 + k;
-#pragma unroll
-        for (int q = 0; q < V; ++q) {
-          const int64_t row = r0 + ms0 + q;
-          ra[q] = (row < pb.M && col < pb.K) ? (PT)A[row * pb.lda + col] : (PT)0;
-        }
-      } else {
-        const int k = tid / (NT / 16), ms0 = (tid % (NT / 16)) * V;
-        const int64_t col = k0 + k;
-#pragma unroll
-        for (int q = 0; q < V; ++q) {
-          const int64_t row = r0 + ms0 + q;
-          ra[q] = (row < pb.M && col < pb.K) ? (PT)A[col * pb.lda + row] : (PT)0;
-        }
-      }
-    }
-    if (!TB) {                            // thread: one column n, V consecutive k
-      const int n = tid % L, ks0 = (tid / L) * V;
-      const int64_t col = c0 + n;
-#pragma unroll
-      for (int q = 0; q < V; ++q) {
-        const int64_t row = k0 + ks0 + q;
-        rb[q] = (row < pb.K && col < pb.N) ? (PT)B[row * pb.ldb + col] : (PT)0;
-      }
-    } else {
-      const int n = tid / (16 / V), ks0 = (tid % (16 / V)) * V;
-      const int64_t col = c0 + n;
-#pragma unroll
-      for (int q = 0; q < V; ++q) {
-        const int64_t row = k0 + ks0 + q;
-        rb[q] = (row < pb.K && col < pb.N) ? (PT)B[col * pb.ldb + row] : (PT)0;
-      }
-    }
+  struct Smem {
+    PT a[2][L * SA];
+    PT b[2][KC * SB];
   };
 
-  // --- compand + pack the registers into LDS buffer `buf` -----------------
-  // W is a template constant here so that the register arrays are indexed
-  // with constants only.
-  auto store_chunk_w = [&](auto wc, int buf, PT ca, PT cbv, PT z, PT zi) {
-    constexpr int W = decltype(wc)::value;
-    constexpr bool colseg = (FORM == TDGEMM_ASYM) && W > 1;
-    PT *a_s = sA[buf];
-    PT *b_s = sB[buf];
-    if (!colseg) {
-      int m, ks0;
-      if (!TA) { m = tid / (16 / V); ks0 = (tid % (16 / V)) * V; }
-      else     { m = tid % L;        ks0 = (tid / L) * V; }
-      const int row = lds_row_of<PT>(m, 1);
+  const Problem &pb;
+  const IT *__restrict__ A;
+  const IT *__restrict__ B;
+  Smem &sm;
+  int tid, lg, lc, wr, wrow, wcol;
+  int64_t r0, c0;
+  // per-thread load coordinates inside a chunk
+  int a_m, a_k;           // first (row, col) this thread loads from A's chunk
+  int b_n, b_k;           // (col, first row) of B's chunk
+  int offA, offB;         // element offsets of (a_m, a_k) and (b_k, b_n) from the chunk corner
+  bool a_row_ok, b_col_ok;
+  Acc accR[RB][CB], accC[RB][CB];
+  PT ra[PF][VA], rb[PF][VB];
+
+  __device__ __forceinline__ Fused(const Problem &pb_, const IT *A_, const IT *B_, Smem &sm_,
+                                   int64_t r0_, int64_t c0_)
+      : pb(pb_), A(A_), B(B_), sm(sm_), r0(r0_), c0(c0_) {
+    tid = threadIdx.x;
+    const int lane = tid & 63;
+    lg = lane >> 4;
+    lc = lane & 15;
+    wr = (tid >> 6) / WC;
+    wrow = wr * 64;
+    wcol = ((tid >> 6) % WC) * 16;
+    if (FORM == TDGEMM_SYM) {
+      // 16 consecutive lanes take 16 consecutive rows, so that their LDS
+      // stores hit distinct banks; the 4 lane groups of a wavefront cover the
+      // 4 column segments of those rows
+      if (!TA) { a_m = (tid >> 6) * 16 + (tid & 15); a_k = ((tid & 63) >> 4) * VA; }
+      else     { a_m = tid % L;                      a_k = (tid / L) * VA; }
+    } else {
+      if (!TA) { a_k = tid % KC;        a_m = (tid / KC) * VA; }
+      else     { a_k = tid / (L / VA);  a_m = (tid % (L / VA)) * VA; }
+    }
+    if (!TB) { b_n = tid % TN;         b_k = (tid / TN) * VB; }
+    else     { b_n = tid / (KC / VB);  b_k = (tid % (KC / VB)) * VB; }
+    offA = TA ? a_k * (int)pb.lda + a_m : a_m * (int)pb.lda + a_k;
+    offB = TB ? b_n * (int)pb.ldb + b_k : b_k * (int)pb.ldb + b_n;
+    a_row_ok = r0 + a_m < pb.M;
+    b_col_ok = c0 + b_n < pb.N;
+#pragma unroll
+    for (int a = 0; a < RB; ++a)
+#pragma unroll
+      for (int b = 0; b < CB; ++b) { accR[a][b] = Mfma<PT>::zero(); accC[a][b] = Mfma<PT>::zero(); }
+  }
+
+  // Raw loads of the chunk starting at inner index k0: a uniform base pointer
+  // plus this thread's fixed offset. With CHECK, out-of-range elements read 0.
+  template <bool CHECK, int S>
+  __device__ __forceinline__ void load(int64_t k0) {
+    const int lda = (int)pb.lda, ldb = (int)pb.ldb;
+    const IT *Ab = TA ? A + k0 * pb.lda + r0 : A + r0 * pb.lda + k0;
+    const IT *Bb = TB ? B + c0 * pb.ldb + k0 : B + k0 * pb.ldb + c0;
+    const int krem = CHECK ? (int)min<int64_t>(pb.K - k0, KC) : KC;    // valid inner columns
+    const int mrem = CHECK ? (int)min<int64_t>(pb.M - r0, L) : L;      // valid rows of the tile
+#pragma unroll
+    for (int q = 0; q < VA; ++q) {
+      // symmetric: (row a_m, col a_k + q); asymmetric: (row a_m + q, col a_k)
+      const bool sym = FORM == TDGEMM_SYM;
+      const int step = sym ? (TA ? lda : 1) : (TA ? 1 : lda);
+      bool ok = true;
+      if (CHECK) ok = sym ? (a_row_ok && a_k + q < krem) : (a_m + q < mrem && a_k < krem);
+      ra[S][q] = ok ? (PT)Ab[offA + q * step] : (PT)0;
+    }
+#pragma unroll
+    for (int q = 0; q < VB; ++q) {
+      const int step = TB ? 1 : ldb;
+      const bool ok = !CHECK || (b_col_ok && b_k + q < krem);
+      rb[S][q] = ok ? (PT)Bb[offB + q * step] : (PT)0;
+    }
+  }
+
+  template <int W>
+  __device__ __forceinline__ static PT compand(PT x, PT c) { return (W == 1) ? x : rint(c * x); }
+
+  // Compand + pack register set S into LDS buffer `buf`, one packed word per
+  // "unit": units 0..UA-1 are words of A (eq. 6 along columns, or eq. 11 along
+  // rows), the rest words of B (eq. 7, or unpacked B). Packing words are
+  // evaluated by Horner's rule from the highest slot; the products with z are
+  // exact (powers of two), so each step is one fused multiply-add.
+  template <int W>
+  static constexpr int units_a() { return VA / W; }
+  template <int W>
+  static constexpr int units_b() { return (FORM == TDGEMM_SYM && W > 1) ? VB / W : VB; }
+
+  template <int W, int S, int U>
+  __device__ __forceinline__ void unit(int buf, PT ca, PT cb, PT z, PT zi) {
+    if (U < units_a<W>()) {
+      constexpr int u = U;
+      PT acc = compand<W>(ra[S][u * W + W - 1], ca);
+#pragma unroll
+      for (int s = W - 2; s >= 0; --s) acc = __builtin_fma(acc, z, compand<W>(ra[S][u * W + s], ca));
+      if (FORM == TDGEMM_SYM) sm.a[buf][lds_row_of<PT>(a_m, 1) * SA + a_k / W + u] = acc;
+      else                    sm.a[buf][lds_row_of<PT>(a_m / W + u, W) * SA + a_k] = acc;
+    } else {
+      constexpr int u = U - units_a<W>();
+      if (FORM == TDGEMM_SYM && W > 1) {
+        PT acc = compand<W>(rb[S][u * W + W - 1], cb);
+#pragma unroll
+        for (int s = W - 2; s >= 0; --s) acc = __builtin_fma(acc, zi, compand<W>(rb[S][u * W + s], cb));
+        sm.b[buf][(b_k / W + u) * SB + b_n] = acc;
+      } else {
+        sm.b[buf][(b_k + u) * SB + b_n] = compand<W>(rb[S][u], cb);
+      }
+    }
+  }
+
+  template <int W, int S, int U0, int U1>
+  __device__ __forceinline__ void units(int buf, PT ca, PT cb, PT z, PT zi) {
+    if constexpr (U0 < U1) {
+      unit<W, S, U0>(buf, ca, cb, z, zi);
+      units<W, S, U0 + 1, U1>(buf, ca, cb, z, zi);
+    }
+  }
+
+  template <int W, int S>
+  __device__ __forceinline__ void store(int buf, PT ca, PT cb, PT z, PT zi) {
+    units<W, S, 0, units_a<W>() + units_b<W>()>(buf, ca, cb, z, zi);
+  }
+
+  // The chunk's MFMAs: packed depth KC / W (symmetric) or KC (asymmetric, W = 1).
+  // Wavefront (wr, wc) multiplies packed row blocks of its 64 output rows by its
+  // column blocks, fragments read one k-step ahead. When STORE is set, the
+  // units of the next chunk (register set S, packing W, into buffer nbuf) are
+  // spread over the k-steps, so that the vector ALU compands and packs while
+  // the matrix cores work.
+  template <int W, bool STORE, int S>
+  __device__ __forceinline__ void mma(int buf, int nbuf, PT ca, PT cb, PT z, PT zi) {
+    constexpr bool SYMW = (FORM == TDGEMM_SYM) || W == 1;
+    constexpr int NKS = SYMW ? KC / (4 * W) : KC / 4;
+    constexpr int RBN = SYMW ? RB : RB / W;
+    constexpr int NU = units_a<W>() + units_b<W>();
+    const PT *as = sm.a[buf] + (16 * RBN * wr + lc) * SA + lg;
+    const PT *bs = sm.b[buf] + lg * SB + wcol + lc;
+    PT af[2][RBN], bf[2][CB];
+#pragma unroll
+    for (int a = 0; a < RBN; ++a) af[0][a] = as[16 * a * SA];
+#pragma unroll
+    for (int b = 0; b < CB; ++b) bf[0][b] = bs[16 * b];
+    static_for<0, NKS>([&](auto ksc) {
+      constexpr int ks = decltype(ksc)::value;
+      constexpr int cur = ks & 1, nxt = cur ^ 1;
+      if constexpr (ks + 1 < NKS) {
+#pragma unroll
+        for (int a = 0; a < RBN; ++a) af[nxt][a] = as[16 * a * SA + 4 * (ks + 1)];
+#pragma unroll
+        for (int b = 0; b < CB; ++b) bf[nxt][b] = bs[4 * (ks + 1) * SB + 16 * b];
+      }
+#pragma unroll
+      for (int a = 0; a < RBN; ++a)
+#pragma unroll
+        for (int b = 0; b < CB; ++b) accR[a][b] = Mfma<PT>::mma(af[cur][a], bf[cur][b], accR[a][b]);
+      if constexpr (STORE)
+        units<W, S, ks * NU / NKS, (ks + 1) * NU / NKS>(nbuf, ca, cb, z, zi);
+      __builtin_amdgcn_sched_barrier(0);
+    });
+  }
+
+  // unpack + reverse companding + l-sum
+  template <int W>
+  __device__ __forceinline__ void finish(PT inv, PT z, PT zi) {
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
       if (W == 1) {
 #pragma unroll
-        for (int q = 0; q < V; ++q) a_s[row * SA + ks0 + q] = ra[q];
-      } else {                            // eq. (6): W consecutive columns per word
-#pragma unroll
-        for (int u = 0; u < V / W; ++u) {
-          PT acc = compand_v(ra[u * W + W - 1], ca, W);
-#pragma unroll
-          for (int s = W - 2; s >= 0; --s) acc = acc * z + compand_v(ra[u * W + s], ca, W);
-          a_s[row * SA + ks0 / W + u] = acc;
-        }
-      }
-    } else {                              // eq. (11): W consecutive rows per word
-      int k, ms0;
-      if (!TA) { k = tid % 16; ms0 = (tid / 16) * V; }
-      else     { k = tid / (NT / 16); ms0 = (tid % (NT / 16)) * V; }
-#pragma unroll
-      for (int u = 0; u < V / W; ++u) {
-        PT acc = compand_v(ra[u * W + W - 1], ca, W);
-#pragma unroll
-        for (int s = W - 2; s >= 0; --s) acc = acc * z + compand_v(ra[u * W + s], ca, W);
-        a_s[lds_row_of<PT>(ms0 / W + u, W) * SA + k] = acc;
-      }
-    }
-    int n, ks0;
-    if (!TB) { n = tid % L;        ks0 = (tid / L) * V; }
-    else     { n = tid / (16 / V); ks0 = (tid % (16 / V)) * V; }
-    if (FORM == TDGEMM_SYM && W > 1) {    // eq. (7): W consecutive rows per word, weights z^-i
-#pragma unroll
-      for (int u = 0; u < V / W; ++u) {
-        PT acc = compand_v(rb[u * W + W - 1], cbv, W);
-#pragma unroll
-        for (int s = W - 2; s >= 0; --s) acc = acc * zi + compand_v(rb[u * W + s], cbv, W);
-        b_s[(ks0 / W + u) * SB + n] = acc;
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < V; ++q) b_s[(ks0 + q) * SB + n] = compand_v(rb[q], cbv, W);
-    }
-  };
-  auto store_chunk = [&](int buf, int W, PT ca, PT cbv, PT z, PT zi) {
-    if (W == 1) store_chunk_w(std::integral_constant<int, 1>(), buf, ca, cbv, z, zi);
-    else if (W == 2) store_chunk_w(std::integral_constant<int, 2>(), buf, ca, cbv, z, zi);
-    else store_chunk_w(std::integral_constant<int, 4>(), buf, ca, cbv, z, zi);
-  };
-
-  // --- MFMA over one chunk -------------------------------------------------
-  auto mfma_chunk = [&](int buf, int W) {
-    const PT *a_s = sA[buf];
-    const PT *b_s = sB[buf];
-    const bool sym = (FORM == TDGEMM_SYM) || W == 1;
-    const int nks = sym ? 4 / W : 4;      // k-steps of 4 in this chunk
-    const int rbn = sym ? RB : RB / W;    // output row blocks
-    for (int ks = 0; ks < nks; ++ks) {
-      PT af[RB], bf[CB];
-#pragma unroll
-      for (int a = 0; a < RB; ++a)
-        if (a < rbn) af[a] = a_s[(16 * a + lc) * SA + 4 * ks + lg];
-#pragma unroll
-      for (int b = 0; b < CB; ++b) bf[b] = b_s[(4 * ks + lg) * SB + wcol + 16 * b + lc];
-#pragma unroll
-      for (int a = 0; a < RB; ++a)
-        if (a < rbn)
-#pragma unroll
-          for (int b = 0; b < CB; ++b) accR[a][b] = Mfma<PT>::mma(af[a], bf[b], accR[a][b]);
-    }
-  };
-
-  // --- unpack + reverse companding + l-sum ---------------------------------
-  auto finish_pair = [&](int W, PT inv, PT z, PT zi) {
-    if (W == 1) {
-#pragma unroll
-      for (int a = 0; a < RB; ++a)
-#pragma unroll
-        for (int b = 0; b < CB; ++b)
+        for (int a = 0; a < RB; ++a)
 #pragma unroll
           for (int r = 0; r < 4; ++r) accC[a][b][r] = accC[a][b][r] + accR[a][b][r];
-    } else if (FORM == TDGEMM_SYM) {      // eqs. (9)-(10), then eq. (5)
+      } else if (FORM == TDGEMM_SYM) {           // eqs. (9)-(10), then eq. (5)
 #pragma unroll
-      for (int a = 0; a < RB; ++a)
-#pragma unroll
-        for (int b = 0; b < CB; ++b)
+        for (int a = 0; a < RB; ++a)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const PT u = rint(accR[a][b][r]);
             const PT t = rint(z * u);
-            const PT rr = u - zi * t;
+            const PT rr = __builtin_fma(-zi, t, u);     // exact: zi * t is a power-of-two multiple
             accC[a][b][r] = accC[a][b][r] + rr * inv;
           }
-    } else if (W == 2) {                  // eqs. (13)-(14), two rows per word
+      } else if (W == 2) {                       // eqs. (13)-(14), two rows per word
 #pragma unroll
-      for (int a = 0; a < RB / 2; ++a)
-#pragma unroll
-        for (int b = 0; b < CB; ++b)
+        for (int a = 0; a < RB / 2; ++a)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const PT v = accR[a][b][r];
@@ -270,11 +274,9 @@ __global__ __launch_bounds__(4 * L) void k_fused(GemmOperands g, const IT *__res
             accC[ra_][b][rr_] = accC[ra_][b][rr_] + q0 * inv;
             accC[ra_][b][rr_ + 1] = accC[ra_][b][rr_ + 1] + q1 * inv;
           }
-    } else {                              // W == 4: four rows per word
+      } else {                                   // W == 4: four rows per word
 #pragma unroll
-      for (int a = 0; a < RB / 4; ++a)
-#pragma unroll
-        for (int b = 0; b < CB; ++b)
+        for (int a = 0; a < RB / 4; ++a)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const PT v = accR[a][b][r];
@@ -290,61 +292,130 @@ __global__ __launch_bounds__(4 * L) void k_fused(GemmOperands g, const IT *__res
             accC[ra_][b][2] = accC[ra_][b][2] + q2 * inv;
             accC[ra_][b][3] = accC[ra_][b][3] + q3 * inv;
           }
+      }
     }
 #pragma unroll
     for (int a = 0; a < RB; ++a)
 #pragma unroll
       for (int b = 0; b < CB; ++b) accR[a][b] = Mfma<PT>::zero();
-  };
-
-  // --- software pipeline over (l, chunk) ------------------------------------
-  // The current pair's settings live in scalars: W, c_A, c_B, z, z^-1, inverse.
-  int64_t l = 0;
-  int kc = 0, buf = 0;
-  int w = prs[0].w;
-  PT ca = (PT)prs[0].c_a, cbv = (PT)prs[0].c_b, inv = (PT)prs[0].inv;
-  PT z = (PT)ldexp(1.0, -prs[0].p), zi = (PT)ldexp(1.0, prs[0].p);
-  load_chunk(0, 0, w);
-  for (;;) {
-    store_chunk(buf, w, ca, cbv, z, zi);
-    __syncthreads();
-    int64_t ln = l;
-    int kcn = kc + 1;
-    if (kcn == NCH) { ln = l + 1; kcn = 0; }
-    const bool more = ln < pb.nL;
-    int wn = w;
-    if (more) {
-      if (ln != l) wn = prs[ln].w;
-      load_chunk(ln, kcn, wn);
-    }
-    mfma_chunk(buf, w);
-    if (kc == NCH - 1) finish_pair(w, inv, z, zi);
-    if (!more) break;
-    if (ln != l) {
-      w = wn;
-      ca = (PT)prs[ln].c_a; cbv = (PT)prs[ln].c_b; inv = (PT)prs[ln].inv;
-      z = (PT)ldexp(1.0, -prs[ln].p); zi = (PT)ldexp(1.0, prs[ln].p);
-    }
-    l = ln; kc = kcn; buf ^= 1;
   }
 
+  struct PairState {
+    int w;
+    PT ca, cb, z, zi, inv;
+  };
+
+  __device__ __forceinline__ static PairState pair_state(const tdgemm_pair &o) {
+    PairState ps;
+    ps.w = o.w;
+    ps.ca = (PT)o.c_a; ps.cb = (PT)o.c_b; ps.inv = (PT)o.inv;
+    ps.z = (PT)ldexp(1.0, -o.p); ps.zi = (PT)ldexp(1.0, o.p);
+    return ps;
+  }
+
+  template <int S>
+  __device__ __forceinline__ void store_any(int buf, const PairState &ps) {
+    if (ps.w == 2) store<2, S>(buf, ps.ca, ps.cb, ps.z, ps.zi);
+    else if (ps.w == 1) store<1, S>(buf, ps.ca, ps.cb, ps.z, ps.zi);
+    else store<4, S>(buf, ps.ca, ps.cb, ps.z, ps.zi);
+  }
+
+  __device__ __forceinline__ void mma_any(int buf, int w) {
+    if (w == 2) mma<2, false, 0>(buf, 0, 0, 0, 0, 0);
+    else if (w == 1) mma<1, false, 0>(buf, 0, 0, 0, 0, 0);
+    else mma<4, false, 0>(buf, 0, 0, 0, 0, 0);
+  }
+
+  __device__ __forceinline__ void finish_any(const PairState &ps) {
+    if (ps.w == 2) finish<2>(ps.inv, ps.z, ps.zi);
+    else if (ps.w == 1) finish<1>(ps.inv, ps.z, ps.zi);
+    else finish<4>(ps.inv, ps.z, ps.zi);
+  }
+
+  // Chunk g (pair l = g / NCH): compand + pack register set S into LDS buffer
+  // g % 2, barrier, issue the raw loads of chunk g + 2 into set S, run chunk g's
+  // MFMAs and, after the pair's last chunk, unpack. The loads of a chunk are in
+  // flight for two chunks of matrix work before they are used.
+  template <bool CHECK, int S>
+  __device__ __forceinline__ void iter(int64_t g, int64_t total, PairState &ps,
+                                       const tdgemm_pair *prs) {
+    const int kc = (int)(g % NCH);
+    if (kc == 0) ps = pair_state(prs[g / NCH]);
+    const int buf = (int)(g & 1);
+    store_any<S>(buf, ps);
+    __syncthreads();
+    const int64_t g2 = g + 2;
+    if (g2 < total) load<CHECK, S>((g2 / NCH) * L + (g2 % NCH) * KC);
+    mma_any(buf, ps.w);
+    if (kc == NCH - 1) finish_any(ps);
+  }
+
+  // walk all pairs of the tile, chunk by chunk
+  template <bool CHECK>
+  __device__ __forceinline__ void run(const tdgemm_pair *prs) {
+    const int64_t total = pb.nL * NCH;
+    PairState ps = pair_state(prs[0]);
+    load<CHECK, 0>(0);
+    if (total > 1) load<CHECK, 1>(KC);
+    for (int64_t g = 0; g < total; g += 2) {
+      iter<CHECK, 0>(g, total, ps, prs);
+      if (g + 1 < total) iter<CHECK, 1>(g + 1, total, ps, prs);
+    }
+  }
+
+  __device__ __forceinline__ void write_c(PT *__restrict__ C) const {
 #pragma unroll
-  for (int a = 0; a < RB; ++a)
+    for (int a = 0; a < RB; ++a)
 #pragma unroll
-    for (int b = 0; b < CB; ++b)
+      for (int b = 0; b < CB; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + 16 * a + 4 * lg + r;
-        const int64_t col = c0 + wcol + 16 * b + lc;
-        if (row < pb.M && col < pb.N) C[row * pb.ldc + col] = accC[a][b][r];
-      }
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = r0 + wrow + 16 * a + 4 * lg + r;
+          const int64_t col = c0 + wcol + 16 * b + lc;
+          if (row < pb.M && col < pb.N) C[row * pb.ldc + col] = accC[a][b][r];
+        }
+  }
+};
+
+template <typename IT, typename PT, int L, int FORM, bool TA, bool TB>
+__global__ __launch_bounds__(4 * L, (L == 64 ? 2 : 1)) void k_fused(GemmOperands g, const IT *__restrict__ A,
+                                                 const IT *__restrict__ B, PT *__restrict__ C,
+                                                 int64_t ntiles, int64_t per_xcd) {
+  typedef Fused<IT, PT, L, FORM, TA, TB> F;
+  __shared__ typename F::Smem sm;
+  // XCD-aware tile order: workgroups are dealt to the 8 XCDs round-robin, so
+  // give each XCD a contiguous range, grouped a few tile-rows at a time so that
+  // the workgroups running together on one XCD share A panels and B slabs in
+  // that XCD's L2.
+  // A workgroup covers L rows and a 64-column slab; an inner kernel of L = 128
+  // is shared by two workgroups with the same pair settings.
+  const int64_t bid = blockIdx.x;
+  const int64_t lin = (bid & 7) * per_xcd + (bid >> 3);
+  if (lin >= ntiles) return;
+  const Problem &pb = g.pb;
+  constexpr int64_t SLABS = L / F::TN;
+  const int64_t nS = pb.nJ * SLABS;
+  constexpr int64_t GROUP = (L == 128) ? 4 : 8;   // tile rows per group: an XCD's
+  const int64_t grp = lin / (GROUP * nS);          // concurrent workgroups form a GROUP x 8 block
+  const int64_t first_i = grp * GROUP;
+  const int64_t gsize = min(GROUP, pb.nI - first_i);
+  const int64_t in_grp = lin - grp * GROUP * nS;
+  const int64_t ti = first_i + in_grp % gsize;
+  const int64_t ts = in_grp / gsize;
+  const int64_t tj = ts / SLABS;
+  F f(pb, A, B, sm, ti * L, ts * F::TN);
+  const tdgemm_pair *prs = g.pairs + (ti * pb.nJ + tj) * pb.nL;
+  const bool interior = (ti + 1) * L <= pb.M && (ts + 1) * F::TN <= pb.N && pb.K % L == 0;
+  if (interior) f.template run<false>(prs);
+  else f.template run<true>(prs);
+  f.write_c(C);
 }
 
 // ---------------------------------------------------------------------------
 template <typename IT, typename PT, int L, int FORM>
 static hipError_t launch_fused_t(const GemmOperands &g, const void *A, const void *B, void *C,
                                  hipStream_t st) {
-  const int64_t ntiles = g.pb.nI * g.pb.nJ;
+  const int64_t ntiles = g.pb.nI * g.pb.nJ * (L / 64);
   const int64_t per_xcd = (ntiles + 7) / 8;
   const dim3 grid((unsigned)(per_xcd * 8));
   const dim3 block(4 * L);

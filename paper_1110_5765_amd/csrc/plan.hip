@@ -98,14 +98,44 @@ struct PlanArgs {
 __device__ __forceinline__ int srow(int W) { return W - 2; }   // s table row of W
 
 __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
-  __shared__ double sh_r[kMaxR], sh_rinv[kMaxR], sh_s[3][kMaxR];
+  __shared__ double sh_r[kMaxR], sh_s[3][kMaxR];
+  __shared__ float sh_fr[3][kMaxR], sh_fs2[3][kMaxR];
+  __shared__ short sh_idx[3][kMaxR];
+  __shared__ unsigned char sh_keep[3][kMaxR];
+  __shared__ int sh_cnt[3];
   const bool snr = a.ctrl == TDGEMM_CTRL_SNR;
   if (snr) {
     for (int k = threadIdx.x; k < a.n_r; k += kThreads) {
-      double r = a.calib_r[k];
-      sh_r[k] = r;
-      sh_rinv[k] = 1.0 / r;
+      sh_r[k] = a.calib_r[k];
       for (int q = 0; q < 3; ++q) sh_s[q][k] = a.calib_s[q * a.n_r + k];
+    }
+    __syncthreads();
+    // non-dominated table points per W row (see argmin_nsr)
+    for (int e = threadIdx.x; e < 3 * a.n_r; e += kThreads) {
+      const int q = e / a.n_r, k = e - (e / a.n_r) * a.n_r;
+      const double sk = sh_s[q][k];
+      bool keep = sk < INFINITY;
+      if (keep) {
+        const double ratio = sk / sh_r[k];
+        for (int k2 = k + 1; k2 < a.n_r && keep; ++k2) {
+          const double s2 = sh_s[q][k2];
+          if (s2 < INFINITY && sh_r[k2] > sh_r[k] && s2 / sh_r[k2] <= ratio) keep = false;
+        }
+      }
+      sh_keep[q][k] = keep ? 1 : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      const int q = threadIdx.x;
+      int c = 0;
+      for (int k = 0; k < a.n_r; ++k) {
+        if (!sh_keep[q][k]) continue;
+        sh_idx[q][c] = (short)k;
+        sh_fr[q][c] = (float)(1.0 / sh_r[k]);
+        sh_fs2[q][c] = (float)(sh_s[q][k] * sh_s[q][k]);
+        ++c;
+      }
+      sh_cnt[q] = c;
     }
   }
   __syncthreads();
@@ -140,7 +170,8 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
       if (v >= a.n_opt) continue;
       const int W = a.w_desc[v];
       if (W == 1 || zero) continue;               // D = 0
-      const int k = argmin_nsr(L_eff, ma, mb, sh_r, sh_rinv, sh_s[srow(W)], a.n_r);
+      const int q = srow(W);
+      const int k = argmin_nsr(L_eff, ma, mb, sh_r, sh_s[q], sh_idx[q], sh_fr[q], sh_fs2[q], sh_cnt[q]);
       kopt[v][t] = k;
       dopt[v][t] = (k < 0) ? kDUnavailable
                            : option_at(W, L_eff, ma, mb, sh_r[k], sh_s[srow(W)][k], a.u_safe).d;
