@@ -142,11 +142,20 @@ tdgemm_status tdgemm_plan(const tdgemm_desc *desc, const void *A, const void *B,
   if (has_work) {
     auto *sa = reinterpret_cast<tdgemm_block_stats *>(p->ws + ly.off_stats_a);
     auto *sb = reinterpret_cast<tdgemm_block_stats *>(p->ws + ly.off_stats_b);
-    hipError_t e = tdg::launch_block_stats(A, desc->in_dtype, desc->M, desc->K, desc->lda,
-                                           desc->trans_a != 0, desc->L, sa, p->stream);
-    if (e == hipSuccess)
-      e = tdg::launch_block_stats(B, desc->in_dtype, desc->K, desc->N, desc->ldb,
-                                  desc->trans_b != 0, desc->L, sb, p->stream);
+    auto *tab = reinterpret_cast<tdg::PlanTable *>(p->ws + ly.off_table);
+    const bool snr = desc->ctrl == TDGEMM_CTRL_SNR;
+    tdg::StatsArgs sargs;
+    sargs.A = A; sargs.B = B;
+    sargs.M = desc->M; sargs.N = desc->N; sargs.K = desc->K;
+    sargs.lda = desc->lda; sargs.ldb = desc->ldb;
+    sargs.ta = desc->trans_a != 0; sargs.tb = desc->trans_b != 0;
+    sargs.nI = ly.nI; sargs.nL = ly.nL; sargs.nJ = ly.nJ;
+    sargs.stats_a = sa; sargs.stats_b = sb;
+    sargs.calib_r = snr ? calib->r : nullptr;
+    sargs.calib_s = snr ? calib->s : nullptr;
+    sargs.n_r = snr ? calib->n_r : 0;
+    sargs.table = snr ? tab : nullptr;
+    hipError_t e = tdg::launch_stats(sargs, desc->in_dtype, desc->L, p->stream);
     if (e == hipSuccess) {
       tdg::PlanLaunch pl;
       pl.pb = problem_of(*desc, ly);
@@ -156,6 +165,7 @@ tdgemm_status tdgemm_plan(const tdgemm_desc *desc, const void *A, const void *B,
       pl.budget = reinterpret_cast<double *>(p->ws + ly.off_budget);
       pl.calib_r = calib ? calib->r : nullptr;
       pl.calib_s = calib ? calib->s : nullptr;
+      pl.table = tab;
       pl.n_r = calib ? calib->n_r : 0;
       pl.ctrl = desc->ctrl;
       pl.n_opt = 0;

@@ -15,6 +15,7 @@ namespace tdg {
 constexpr int kThreads = 256;          // threads per workgroup of every kernel
 constexpr int kWave = 64;              // CDNA wavefront width
 constexpr double kDUnavailable = 1e300;  // D of an option the calibration cannot supply
+constexpr int kMaxR = 512;             // calibration grid points
 
 // ---------------------------------------------------------------------------
 // Compensated sums. A running sum is a pair (s, c): s the rounded sum, c the
@@ -195,10 +196,19 @@ __device__ __forceinline__ int argmin_nsr(double L_eff, const BlockMoments &a, c
 }
 
 // ---------------------------------------------------------------------------
+// Non-dominated calibration points per W row (W = 2, 3, 4), ascending R: grid
+// index, 1/R and s^2 in FP32 (see argmin_nsr). Built by the statistics launch.
+struct PlanTable {
+  int32_t cnt[4];
+  int16_t idx[3][kMaxR];
+  float fr[3][kMaxR];
+  float fs2[3][kMaxR];
+};
+
 // Workspace layout shared by the host code and the kernels.
 struct Layout {
   int64_t nI, nL, nJ, n_pairs;
-  size_t off_stats_a, off_stats_b, off_pairs, off_budget, total;
+  size_t off_stats_a, off_stats_b, off_pairs, off_budget, off_table, total;
 };
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -214,6 +224,7 @@ __host__ inline Layout make_layout(int64_t M, int64_t N, int64_t K, int L) {
   ly.off_stats_b = off; off = align256(off + sizeof(tdgemm_block_stats) * ly.nL * ly.nJ);
   ly.off_pairs = off;   off = align256(off + sizeof(tdgemm_pair) * ly.n_pairs);
   ly.off_budget = off;  off = align256(off + sizeof(double) * ly.nI * ly.nJ);
+  ly.off_table = off;   off = align256(off + sizeof(PlanTable));
   ly.total = off;
   return ly;
 }

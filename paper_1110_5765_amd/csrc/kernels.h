@@ -7,6 +7,20 @@
 
 namespace tdg {
 
+// Statistics of every block of A and B, and (table != nullptr) the
+// non-dominated calibration table, in one launch.
+struct StatsArgs {
+  const void *A, *B;
+  int64_t M, N, K, lda, ldb;
+  int ta, tb;
+  int64_t nI, nL, nJ;
+  tdgemm_block_stats *stats_a;   // [nI][nL]
+  tdgemm_block_stats *stats_b;   // [nL][nJ]
+  const double *calib_r, *calib_s;
+  int n_r;
+  PlanTable *table;
+};
+
 struct PlanLaunch {
   Problem pb;
   const tdgemm_block_stats *stats_a;
@@ -15,6 +29,7 @@ struct PlanLaunch {
   double *budget;
   const double *calib_r;
   const double *calib_s;
+  const PlanTable *table;
   int n_r;
   int ctrl;
   int n_opt;
@@ -31,8 +46,7 @@ struct GemmOperands {
   const tdgemm_pair *pairs;   // [n_pairs]
 };
 
-hipError_t launch_block_stats(const void *X, int dtype, int64_t rows, int64_t cols, int64_t ld,
-                              bool tr, int L, tdgemm_block_stats *out, hipStream_t st);
+hipError_t launch_stats(const StatsArgs &a, int dtype, int L, hipStream_t st);
 hipError_t launch_plan(const PlanLaunch &p, hipStream_t st);
 
 // staged path

@@ -6,65 +6,163 @@
 namespace tdg {
 
 // ---------------------------------------------------------------------------
-// One workgroup per L x L block of a matrix X (rows x cols logically; stored
-// transposed when TR). Threads stride through the block so that consecutive
-// lanes read consecutive addresses: along a row when X is stored as given,
-// along a column of the logical block when it is stored transposed.
-// Writes min, max, the compensated sum of squares (TwoProduct via fma, TwoSum)
-// and the number of valid elements.
-template <typename T, bool TR>
-__global__ __launch_bounds__(kThreads) void k_block_stats(const T *__restrict__ X, int64_t rows,
-                                                          int64_t cols, int64_t ld, int L,
-                                                          int64_t ncb, tdgemm_block_stats *out) {
-  const int64_t rb = blockIdx.y, cb = blockIdx.x;
-  const int64_t r0 = rb * L, c0 = cb * L;
-  const int vr = (int)min<int64_t>(L, rows - r0);
-  const int vc = (int)min<int64_t>(L, cols - c0);
-  double mn = INFINITY, mx = -INFINITY;
-  CSum acc{0.0, 0.0};
-  const int n = L * L;
-  for (int e = threadIdx.x; e < n; e += kThreads) {
-    int r, c;
-    if (!TR) { r = e / L; c = e - r * L; }
-    else     { c = e / L; r = e - c * L; }
-    if (r < vr && c < vc) {
-      double x = TR ? (double)X[(c0 + c) * ld + (r0 + r)] : (double)X[(r0 + r) * ld + (c0 + c)];
-      mn = fmin(mn, x);
-      mx = fmax(mx, x);
-      double p = x * x;
-      double pe = __builtin_fma(x, x, -p);
-      acc = csum_add(acc, p);
-      acc.c = acc.c + pe;
-    }
-  }
+// Block statistics. The result of a block does not depend on the order in
+// which its elements are visited (min and max are exact, the sum of squares is
+// compensated and rounded once), so every block is read in its stored layout:
+// a transposed operand is the same set of elements.
+
+struct StatAcc {
+  double mn, mx;
+  CSum s;
+};
+
+__device__ __forceinline__ void stat_add(StatAcc &a, double x) {
+  a.mn = fmin(a.mn, x);
+  a.mx = fmax(a.mx, x);
+  const double p = x * x;
+  const double pe = __builtin_fma(x, x, -p);     // x^2 = p + pe exactly
+  a.s = csum_add(a.s, p);
+  a.s.c = a.s.c + pe;
+}
+
+__device__ __forceinline__ StatAcc stat_merge(const StatAcc &a, const StatAcc &b) {
+  return StatAcc{fmin(a.mn, b.mn), fmax(a.mx, b.mx), csum_merge(a.s, b.s)};
+}
+
+__device__ __forceinline__ StatAcc stat_shfl_xor(const StatAcc &a, int off) {
+  return StatAcc{__shfl_xor(a.mn, off), __shfl_xor(a.mx, off),
+                 CSum{__shfl_xor(a.s.s, off), __shfl_xor(a.s.c, off)}};
+}
+
+// One workgroup: the stored block of vr x vc valid elements at X (leading
+// dimension ld). A full block whose rows start on 16-byte boundaries is read
+// with 16-byte loads, all issued before the first use; other blocks element by
+// element with bounds checks.
+template <typename T, int L>
+__device__ __forceinline__ void block_stats(const T *__restrict__ X, int64_t ld, int vr, int vc,
+                                            tdgemm_block_stats *out) {
+  constexpr int V = 16 / (int)sizeof(T);            // elements per 16-byte load
+  constexpr int RV = L / V;                         // loads per row
+  constexpr int NV = L * L / V / kThreads;          // loads per thread
+  typedef T vec_t __attribute__((ext_vector_type(V)));
+  const int tid = threadIdx.x;
+  StatAcc acc0{INFINITY, -INFINITY, CSum{0.0, 0.0}}, acc1 = acc0;
+  const bool vec = vr == L && vc == L && ((uintptr_t)X % 16) == 0 &&
+                   ((ld * (int64_t)sizeof(T)) % 16) == 0;
+  if (vec) {
+    vec_t v[NV];
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    mn = fmin(mn, __shfl_xor(mn, off));
-    mx = fmax(mx, __shfl_xor(mx, off));
-    CSum y{__shfl_xor(acc.s, off), __shfl_xor(acc.c, off)};
-    acc = csum_merge(acc, y);
-  }
-  __shared__ double s_mn[kThreads / kWave], s_mx[kThreads / kWave], s_s[kThreads / kWave],
-      s_c[kThreads / kWave];
-  const int w = threadIdx.x / kWave;
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-    s_mn[w] = mn; s_mx[w] = mx; s_s[w] = acc.s; s_c[w] = acc.c;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    CSum t{s_s[0], s_c[0]};
-    double tmn = s_mn[0], tmx = s_mx[0];
-    for (int q = 1; q < kThreads / kWave; ++q) {
-      t = csum_merge(t, CSum{s_s[q], s_c[q]});
-      tmn = fmin(tmn, s_mn[q]);
-      tmx = fmax(tmx, s_mx[q]);
+    for (int q = 0; q < NV; ++q) {
+      const int e = tid + kThreads * q;
+      v[q] = *reinterpret_cast<const vec_t *>(X + (int64_t)(e / RV) * ld + (e % RV) * V);
     }
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+#pragma unroll
+      for (int c = 0; c < V; ++c) stat_add((q & 1) ? acc1 : acc0, (double)v[q][c]);
+  } else {
+    for (int e = tid; e < L * L; e += kThreads) {
+      const int r = e / L, c = e - (e / L) * L;
+      if (r < vr && c < vc) stat_add(acc0, (double)X[(int64_t)r * ld + c]);
+    }
+  }
+  StatAcc acc = stat_merge(acc0, acc1);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc = stat_merge(acc, stat_shfl_xor(acc, off));
+  __shared__ StatAcc s_w[kThreads / kWave];
+  if ((tid & (kWave - 1)) == 0) s_w[tid / kWave] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    StatAcc t = s_w[0];
+    for (int q = 1; q < kThreads / kWave; ++q) t = stat_merge(t, s_w[q]);
     tdgemm_block_stats st;
-    st.mn = tmn;
-    st.mx = tmx;
-    st.sumsq = csum_value(t);
+    st.mn = t.mn;
+    st.mx = t.mx;
+    st.sumsq = csum_value(t.s);
     st.n = (int64_t)vr * vc;
-    out[rb * ncb + cb] = st;
+    *out = st;
+  }
+}
+
+// Non-dominated points of the calibration grid, per W row (see argmin_nsr):
+// point k is kept when s[k] is finite and s[k] / R[k] is below s[k'] / R[k']
+// for every k' > k (R strictly ascending). One wavefront per row; lane q owns
+// the points [8q, 8q + 8), suffix minima and the compaction run across lanes.
+__device__ __forceinline__ void build_table(const double *__restrict__ r,
+                                            const double *__restrict__ s, int n_r,
+                                            PlanTable *tab) {
+  constexpr int PER = kMaxR / kWave;
+  const int q = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  if (q >= 3) return;
+  double ratio[PER];
+  double cmin = INFINITY;
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int k = lane * PER + m;
+    ratio[m] = INFINITY;
+    if (k < n_r) {
+      const double sk = s[q * n_r + k];
+      if (sk < INFINITY) ratio[m] = sk / r[k];
+    }
+    cmin = fmin(cmin, ratio[m]);
+  }
+  double suf = cmin;                                // min over lanes >= this one
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const double o = __shfl_down(suf, off);
+    if (lane + off < kWave) suf = fmin(suf, o);
+  }
+  double run = __shfl_down(suf, 1);                 // min over lanes > this one
+  if (lane == kWave - 1) run = INFINITY;
+  bool keep[PER];
+  int c = 0;
+#pragma unroll
+  for (int m = PER - 1; m >= 0; --m) {
+    keep[m] = ratio[m] < run;                       // also false for s = +inf
+    run = fmin(run, ratio[m]);
+    c += keep[m] ? 1 : 0;
+  }
+  int pre = c;                                      // inclusive prefix over lanes
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int o = __shfl_up(pre, off);
+    if (lane >= off) pre += o;
+  }
+  int pos = pre - c;
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    if (!keep[m]) continue;
+    const int k = lane * PER + m;
+    const double sk = s[q * n_r + k];
+    tab->idx[q][pos] = (short)k;
+    tab->fr[q][pos] = (float)(1.0 / r[k]);
+    tab->fs2[q][pos] = (float)(sk * sk);
+    ++pos;
+  }
+  if (lane == kWave - 1) tab->cnt[q] = pre;
+}
+
+// Grid: one workgroup per block of A, then one per block of B, then (SNR
+// control) one that builds the calibration table.
+template <typename T, int L>
+__global__ __launch_bounds__(kThreads) void k_stats(StatsArgs a) {
+  const int64_t nbA = a.nI * a.nL, nbB = a.nL * a.nJ;
+  const int64_t b = blockIdx.x;
+  if (b < nbA) {                                    // block (i, l) of A, M x K
+    const int64_t i = b / a.nL, l = b - (b / a.nL) * a.nL;
+    const int vm = (int)min<int64_t>(L, a.M - i * L), vk = (int)min<int64_t>(L, a.K - l * L);
+    const T *X = static_cast<const T *>(a.A);
+    if (a.ta) block_stats<T, L>(X + (l * L) * a.lda + i * L, a.lda, vk, vm, &a.stats_a[b]);
+    else      block_stats<T, L>(X + (i * L) * a.lda + l * L, a.lda, vm, vk, &a.stats_a[b]);
+  } else if (b < nbA + nbB) {                       // block (l, j) of B, K x N
+    const int64_t bb = b - nbA;
+    const int64_t l = bb / a.nJ, j = bb - (bb / a.nJ) * a.nJ;
+    const int vk = (int)min<int64_t>(L, a.K - l * L), vn = (int)min<int64_t>(L, a.N - j * L);
+    const T *X = static_cast<const T *>(a.B);
+    if (a.tb) block_stats<T, L>(X + (j * L) * a.ldb + l * L, a.ldb, vn, vk, &a.stats_b[bb]);
+    else      block_stats<T, L>(X + (l * L) * a.ldb + j * L, a.ldb, vk, vn, &a.stats_b[bb]);
+  } else {
+    build_table(a.calib_r, a.calib_s, a.n_r, a.table);
   }
 }
 
@@ -74,8 +172,16 @@ __global__ __launch_bounds__(kThreads) void k_block_stats(const T *__restrict__ 
 // noise over the calibrated grid), then prunes top-down (Sec. 6): while the
 // exactly rounded sum of the current D exceeds the budget, the pair with the
 // largest D (lowest l on ties) drops to the next smaller allowed W.
+//
+// When every pair's D strictly decreases from one allowed W to the next (the
+// usual case), the greedy removes the "entries" (pair l at level v, value
+// D_v(l) > 0) in the order of descending D, lowest l first among equals: an
+// entry of l only becomes current once the larger entries of l are gone, and
+// they come earlier in that order anyway. The sum after t removals is then
+// non-increasing in t, and the greedy's stopping point -- the first t whose
+// exactly rounded sum is within the budget -- is found by bisection over t
+// from the entries' ranks. Otherwise the greedy runs step by step.
 constexpr int kMaxT = 8;          // up to 512 subblocks along K
-constexpr int kMaxR = 512;        // calibration grid points
 constexpr int kMaxOpt = 3;        // allowed W levels: at most {4, 2, 1}
 
 struct PlanArgs {
@@ -86,6 +192,7 @@ struct PlanArgs {
   double *budget;                      // [nI][nJ]
   const double *calib_r;               // [n_r]
   const double *calib_s;               // [3][n_r]
+  const PlanTable *table;
   int n_r;
   int ctrl;
   int n_opt;                           // allowed W levels, descending in w_desc
@@ -97,45 +204,30 @@ struct PlanArgs {
 
 __device__ __forceinline__ int srow(int W) { return W - 2; }   // s table row of W
 
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// TT: subblocks per lane the kernel is compiled for (T = ceil(nL / 64) <= TT).
+template <int TT>
 __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
-  __shared__ double sh_r[kMaxR], sh_s[3][kMaxR];
+  constexpr int kEnt = (kMaxOpt - 1) * TT * kWave;   // entry slots per wavefront
   __shared__ float sh_fr[3][kMaxR], sh_fs2[3][kMaxR];
   __shared__ short sh_idx[3][kMaxR];
-  __shared__ unsigned char sh_keep[3][kMaxR];
   __shared__ int sh_cnt[3];
+  __shared__ double sh_ent[kThreads / kWave][kEnt];
   const bool snr = a.ctrl == TDGEMM_CTRL_SNR;
   if (snr) {
-    for (int k = threadIdx.x; k < a.n_r; k += kThreads) {
-      sh_r[k] = a.calib_r[k];
-      for (int q = 0; q < 3; ++q) sh_s[q][k] = a.calib_s[q * a.n_r + k];
-    }
-    __syncthreads();
-    // non-dominated table points per W row (see argmin_nsr)
-    for (int e = threadIdx.x; e < 3 * a.n_r; e += kThreads) {
-      const int q = e / a.n_r, k = e - (e / a.n_r) * a.n_r;
-      const double sk = sh_s[q][k];
-      bool keep = sk < INFINITY;
-      if (keep) {
-        const double ratio = sk / sh_r[k];
-        for (int k2 = k + 1; k2 < a.n_r && keep; ++k2) {
-          const double s2 = sh_s[q][k2];
-          if (s2 < INFINITY && sh_r[k2] > sh_r[k] && s2 / sh_r[k2] <= ratio) keep = false;
-        }
+    if (threadIdx.x < 3) sh_cnt[threadIdx.x] = a.table->cnt[threadIdx.x];
+    for (int e = threadIdx.x; e < 3 * kMaxR; e += kThreads) {
+      const int q = e / kMaxR, k = e - (e / kMaxR) * kMaxR;
+      if (k < a.table->cnt[q]) {
+        sh_idx[q][k] = a.table->idx[q][k];
+        sh_fr[q][k] = a.table->fr[q][k];
+        sh_fs2[q][k] = a.table->fs2[q][k];
       }
-      sh_keep[q][k] = keep ? 1 : 0;
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-      const int q = threadIdx.x;
-      int c = 0;
-      for (int k = 0; k < a.n_r; ++k) {
-        if (!sh_keep[q][k]) continue;
-        sh_idx[q][c] = (short)k;
-        sh_fr[q][c] = (float)(1.0 / sh_r[k]);
-        sh_fs2[q][c] = (float)(sh_s[q][k] * sh_s[q][k]);
-        ++c;
-      }
-      sh_cnt[q] = c;
     }
   }
   __syncthreads();
@@ -147,12 +239,12 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
   const int T = (int)((pb.nL + kWave - 1) / kWave);
 
   // per-(level, t) noise and chosen grid index, and current level per t
-  double dopt[kMaxOpt][kMaxT];
-  int kopt[kMaxOpt][kMaxT];
-  int level[kMaxT];
+  double dopt[kMaxOpt][TT];
+  int kopt[kMaxOpt][TT];
+  int level[TT];
   CSum sig{0.0, 0.0};
 #pragma unroll
-  for (int t = 0; t < kMaxT; ++t) {
+  for (int t = 0; t < TT; ++t) {
     level[t] = 0;
 #pragma unroll
     for (int v = 0; v < kMaxOpt; ++v) { dopt[v][t] = 0.0; kopt[v][t] = -1; }
@@ -163,65 +255,151 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
     const BlockMoments ma = moments(a.stats_a[i * pb.nL + l]);
     const BlockMoments mb = moments(a.stats_b[l * pb.nJ + j]);
     sig = csum_add(sig, (L_eff * (ma.sigma * ma.sigma)) * (mb.sigma * mb.sigma));
-    if (!snr) continue;
-    const bool zero = (ma.amax == 0.0 || mb.amax == 0.0);
-#pragma unroll
-    for (int v = 0; v < kMaxOpt; ++v) {
-      if (v >= a.n_opt) continue;
+    if (!snr || ma.amax == 0.0 || mb.amax == 0.0) continue;   // D = 0
+#pragma unroll 1
+    for (int v = 0; v < a.n_opt; ++v) {
       const int W = a.w_desc[v];
-      if (W == 1 || zero) continue;               // D = 0
+      if (W == 1) continue;                       // D = 0
       const int q = srow(W);
-      const int k = argmin_nsr(L_eff, ma, mb, sh_r, sh_s[q], sh_idx[q], sh_fr[q], sh_fs2[q], sh_cnt[q]);
-      kopt[v][t] = k;
-      dopt[v][t] = (k < 0) ? kDUnavailable
-                           : option_at(W, L_eff, ma, mb, sh_r[k], sh_s[srow(W)][k], a.u_safe).d;
+      const double *s = a.calib_s + q * a.n_r;
+      const int k = argmin_nsr(L_eff, ma, mb, a.calib_r, s, sh_idx[q], sh_fr[q], sh_fs2[q], sh_cnt[q]);
+      const double d = (k < 0) ? kDUnavailable
+                               : option_at(W, L_eff, ma, mb, a.calib_r[k], s[k], a.u_safe).d;
+#pragma unroll
+      for (int u = 0; u < kMaxOpt; ++u)
+        if (u == v) { dopt[u][t] = d; kopt[u][t] = k; }
     }
   }
 
+  // level of slot t after removing every entry ranked below `cut`
+  auto total_at = [&](const int (&rank)[kMaxOpt - 1][TT], int cut) {
+    CSum tot{0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+      int lv = 0;
+#pragma unroll
+      for (int v = 0; v < kMaxOpt - 1; ++v) lv += (rank[v][t] < cut) ? 1 : 0;
+      double dv = 0.0;
+#pragma unroll
+      for (int v = 0; v < kMaxOpt; ++v) if (lv == v) dv = dopt[v][t];
+      tot = csum_add(tot, dv);
+    }
+    return wave_csum(tot);
+  };
+
   double budget = 0.0;
-  if (snr) {
+  const int n_ent = a.n_opt - 1;                  // entry levels 0 .. n_opt - 2
+  if (snr && n_ent > 0) {
     budget = a.snr_lin * wave_csum(sig);
-    for (;;) {
-      CSum tot{0.0, 0.0};
+    // does every pair's D decrease strictly along its entries (and weakly to the floor)?
+    bool mono = true;
 #pragma unroll
-      for (int t = 0; t < kMaxT; ++t) {
-        double dv = 0.0;
+    for (int t = 0; t < TT; ++t)
 #pragma unroll
-        for (int v = 0; v < kMaxOpt; ++v) if (level[t] == v) dv = dopt[v][t];
-        tot = csum_add(tot, dv);
+      for (int v = 0; v + 1 < kMaxOpt; ++v) {
+        if (v + 1 >= a.n_opt) continue;
+        const double d0 = dopt[v][t], d1 = dopt[v + 1][t];
+        if (!(d1 <= d0)) mono = false;
+        if (v + 1 < n_ent && d1 > 0.0 && !(d0 > d1)) mono = false;
       }
-      const double total = wave_csum(tot);
-      if (!(total > budget)) break;
-      // candidate with the largest current D, lowest l among equals
-      double bd = -INFINITY;
-      int64_t bl = INT64_MAX;
+    if (__all(mono)) {
+      double *ent = sh_ent[threadIdx.x / kWave];
 #pragma unroll
-      for (int t = 0; t < kMaxT; ++t) {
-        const int64_t l = lane + (int64_t)kWave * t;
-        if (t >= T || l >= pb.nL || level[t] >= a.n_opt - 1) continue;
-        double dv = 0.0;
+      for (int v = 0; v < kMaxOpt - 1; ++v)
 #pragma unroll
-        for (int v = 0; v < kMaxOpt; ++v) if (level[t] == v) dv = dopt[v][t];
-        if (dv > bd || (dv == bd && l < bl)) { bd = dv; bl = l; }
+        for (int t = 0; t < TT; ++t)
+          if (v < n_ent && t < T) ent[(v * T + t) * kWave + lane] = dopt[v][t];
+      wave_sync_lds();
+      // rank of each own entry with D > 0: entries with a larger D, or equal D and lower l
+      int rank[kMaxOpt - 1][TT];
+#pragma unroll
+      for (int v = 0; v < kMaxOpt - 1; ++v)
+#pragma unroll
+        for (int t = 0; t < TT; ++t) rank[v][t] = (v < n_ent && dopt[v][t] > 0.0) ? 0 : INT_MAX;
+      const int nslot = n_ent * T * kWave;
+      for (int sidx = 0; sidx < nslot; ++sidx) {
+        const double ds = ent[sidx];
+        const int ls = ((sidx / kWave) % T) * kWave + (sidx & (kWave - 1));
+#pragma unroll
+        for (int v = 0; v < kMaxOpt - 1; ++v)
+#pragma unroll
+          for (int t = 0; t < TT; ++t) {
+            const double de = dopt[v][t];
+            const int le = t * kWave + lane;
+            if (ds > de || (ds == de && ls < le)) rank[v][t] += (rank[v][t] != INT_MAX) ? 1 : 0;
+          }
+      }
+      int n_pos = 0;
+#pragma unroll
+      for (int v = 0; v < kMaxOpt - 1; ++v)
+#pragma unroll
+        for (int t = 0; t < TT; ++t)
+          n_pos += __popcll(__ballot(rank[v][t] != INT_MAX));
+      int cut;
+      if (!(total_at(rank, n_pos) <= budget)) {
+        cut = INT_MAX;                            // the greedy empties every entry
+      } else {
+        int lo = 0, hi = n_pos;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (total_at(rank, mid) <= budget) hi = mid;
+          else lo = mid + 1;
+        }
+        cut = lo;
       }
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        double od = __shfl_xor(bd, off);
-        int64_t ol = __shfl_xor(bl, off);
-        if (od > bd || (od == bd && ol < bl)) { bd = od; bl = ol; }
-      }
-      if (bl == INT64_MAX) break;                 // everything already at the lowest W
-      if ((bl & (kWave - 1)) == lane) {
-        const int tt = (int)(bl / kWave);
+      for (int t = 0; t < TT; ++t) {
+        int lv = 0;
 #pragma unroll
-        for (int t = 0; t < kMaxT; ++t) if (t == tt) level[t] += 1;
+        for (int v = 0; v < kMaxOpt - 1; ++v)
+          lv += (v < n_ent && (cut == INT_MAX || rank[v][t] < cut)) ? 1 : 0;
+        level[t] = lv;
+      }
+    } else {
+      for (;;) {
+        CSum tot{0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < TT; ++t) {
+          double dv = 0.0;
+#pragma unroll
+          for (int v = 0; v < kMaxOpt; ++v) if (level[t] == v) dv = dopt[v][t];
+          tot = csum_add(tot, dv);
+        }
+        const double total = wave_csum(tot);
+        if (!(total > budget)) break;
+        // candidate with the largest current D, lowest l among equals
+        double bd = -INFINITY;
+        int64_t bl = INT64_MAX;
+#pragma unroll
+        for (int t = 0; t < TT; ++t) {
+          const int64_t l = lane + (int64_t)kWave * t;
+          if (t >= T || l >= pb.nL || level[t] >= a.n_opt - 1) continue;
+          double dv = 0.0;
+#pragma unroll
+          for (int v = 0; v < kMaxOpt; ++v) if (level[t] == v) dv = dopt[v][t];
+          if (dv > bd || (dv == bd && l < bl)) { bd = dv; bl = l; }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          double od = __shfl_xor(bd, off);
+          int64_t ol = __shfl_xor(bl, off);
+          if (od > bd || (od == bd && ol < bl)) { bd = od; bl = ol; }
+        }
+        if (bl == INT64_MAX) break;               // everything already at the lowest W
+        if ((bl & (kWave - 1)) == lane) {
+          const int tt = (int)(bl / kWave);
+#pragma unroll
+          for (int t = 0; t < TT; ++t) if (t == tt) level[t] += 1;
+        }
       }
     }
+  } else if (snr) {
+    budget = a.snr_lin * wave_csum(sig);
   }
 
   // final records
 #pragma unroll
-  for (int t = 0; t < kMaxT; ++t) {
+  for (int t = 0; t < TT; ++t) {
     if (t >= T) continue;
     const int64_t l = lane + (int64_t)kWave * t;
     if (l >= pb.nL) continue;
@@ -238,7 +416,7 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
       if (W == 1) o = option_native();
       else if (zero) o = option_zero(W, a.u_safe);
       else if (k < 0) { o = option_zero(W, a.u_safe); o.d = kDUnavailable; o.s_rep = INFINITY; }
-      else o = option_at(W, L_eff, ma, mb, sh_r[k], sh_s[srow(W)][k], a.u_safe);
+      else o = option_at(W, L_eff, ma, mb, a.calib_r[k], a.calib_s[srow(W) * a.n_r + k], a.u_safe);
     } else {
       const int W = a.fixed_w;
       if (W == 1) o = option_native();
@@ -252,24 +430,23 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-template <typename T>
-static hipError_t launch_stats_t(const void *X, int64_t rows, int64_t cols, int64_t ld, bool tr,
-                                 int L, tdgemm_block_stats *out, hipStream_t st) {
-  const int64_t nrb = (rows + L - 1) / L, ncb = (cols + L - 1) / L;
-  dim3 grid((unsigned)ncb, (unsigned)nrb);
-  if (tr)
-    hipLaunchKernelGGL((k_block_stats<T, true>), grid, dim3(kThreads), 0, st, (const T *)X, rows,
-                       cols, ld, L, ncb, out);
-  else
-    hipLaunchKernelGGL((k_block_stats<T, false>), grid, dim3(kThreads), 0, st, (const T *)X, rows,
-                       cols, ld, L, ncb, out);
-  return hipGetLastError();
+template <typename T, int L>
+static void launch_stats_t(const StatsArgs &a, unsigned blocks, hipStream_t st) {
+  hipLaunchKernelGGL((k_stats<T, L>), dim3(blocks), dim3(kThreads), 0, st, a);
 }
 
-hipError_t launch_block_stats(const void *X, int dtype, int64_t rows, int64_t cols, int64_t ld,
-                              bool tr, int L, tdgemm_block_stats *out, hipStream_t st) {
-  return dtype == TDGEMM_F64 ? launch_stats_t<double>(X, rows, cols, ld, tr, L, out, st)
-                             : launch_stats_t<float>(X, rows, cols, ld, tr, L, out, st);
+hipError_t launch_stats(const StatsArgs &a, int dtype, int L, hipStream_t st) {
+  const int64_t blocks = a.nI * a.nL + a.nL * a.nJ + (a.table ? 1 : 0);
+  if (blocks == 0) return hipSuccess;
+  const unsigned nb = (unsigned)blocks;
+  if (dtype == TDGEMM_F64) {
+    if (L == 64) launch_stats_t<double, 64>(a, nb, st);
+    else         launch_stats_t<double, 128>(a, nb, st);
+  } else {
+    if (L == 64) launch_stats_t<float, 64>(a, nb, st);
+    else         launch_stats_t<float, 128>(a, nb, st);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_plan(const PlanLaunch &p, hipStream_t st) {
@@ -281,6 +458,7 @@ hipError_t launch_plan(const PlanLaunch &p, hipStream_t st) {
   a.budget = p.budget;
   a.calib_r = p.calib_r;
   a.calib_s = p.calib_s;
+  a.table = p.table;
   a.n_r = p.n_r;
   a.ctrl = p.ctrl;
   a.n_opt = p.n_opt;
@@ -292,7 +470,11 @@ hipError_t launch_plan(const PlanLaunch &p, hipStream_t st) {
   a.snr_lin = p.snr_lin;
   const int64_t tiles = p.pb.nI * p.pb.nJ;
   const unsigned blocks = (unsigned)((tiles + (kThreads / kWave) - 1) / (kThreads / kWave));
-  hipLaunchKernelGGL(k_plan, dim3(blocks), dim3(kThreads), 0, st, a);
+  const int64_t T = (p.pb.nL + kWave - 1) / kWave;
+  if (T <= 1)      hipLaunchKernelGGL(k_plan<1>, dim3(blocks), dim3(kThreads), 0, st, a);
+  else if (T <= 2) hipLaunchKernelGGL(k_plan<2>, dim3(blocks), dim3(kThreads), 0, st, a);
+  else if (T <= 4) hipLaunchKernelGGL(k_plan<4>, dim3(blocks), dim3(kThreads), 0, st, a);
+  else             hipLaunchKernelGGL(k_plan<kMaxT>, dim3(blocks), dim3(kThreads), 0, st, a);
   return hipGetLastError();
 }
 

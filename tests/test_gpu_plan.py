@@ -1,0 +1,90 @@
+"""GPU parity of the plan alone (statistics, per-pair options, Sec. 6 pruning)
+on inputs chosen to stress the pruning: equal noise values across subblocks,
+more than 64 subblocks along K, calibration tables under which D does not
+decrease with W (the step-by-step greedy) and tables with no usable W = 4
+point. Records and budgets must equal the oracle's bit for bit."""
+import zlib
+
+import numpy as np
+import pytest
+
+from oracle import control as ct
+from oracle import pipeline as pl
+from tests.gpu_common import compare_plan, log, oracle_cfg, to_dev
+from tests.oracle_tables import tables
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def td():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1110_5765_amd import tdgemm
+    return tdgemm
+
+
+def _calib(kind, L, form):
+    tabs = tables(L, form, "f64", (2, 4))
+    r = tabs[2].r
+    if kind == "scaled_w4":          # W = 4 cheaper than W = 2: D need not fall with W
+        tabs = {2: tabs[2], 4: ct.CalibTable(r.copy(), tabs[2].s * 0.25)}
+    elif kind == "no_w4":            # no usable W = 4 point: D_4 is the "unavailable" value
+        tabs = {2: tabs[2], 4: ct.CalibTable(r.copy(), np.full(r.size, np.inf))}
+    return tabs
+
+
+CASES = [
+    # name, M, K, N, L, form, snr, w_allowed, inputs, calib
+    ("ties_equal_blocks", 128, 384, 128, 64, "sym", 83.0, (1, 2, 4), "tiled", "std"),
+    ("many_l_T2", 128, 64 * 70, 128, 64, "sym", 30.0, (1, 2, 4), "gauss", "std"),
+    ("many_l_T5_ragged", 64, 64 * 300 + 17, 70, 64, "asym", 25.0, (1, 2, 4), "laplace", "std"),
+    ("L128_many_l", 128, 128 * 70, 128, 128, "sym", 35.0, (1, 2, 4), "gauss", "std"),
+    ("nonmono_fallback", 192, 640, 128, 64, "sym", 86.0, (1, 2, 4), "gauss", "scaled_w4"),
+    ("unavailable_w4", 128, 512, 192, 64, "sym", 80.0, (1, 2, 4), "laplace", "no_w4"),
+    ("deep_prune_w2_only", 256, 1024, 64, 64, "sym", 80.0, (1, 2), "laplace", "std"),
+]
+
+
+def _inputs(kind, M, K, N, seed):
+    r = np.random.default_rng(seed)
+    if kind == "tiled":              # the same 64 x 64 block repeated along K
+        a = r.standard_normal((M, 64))
+        b = r.standard_normal((64, N))
+        return np.tile(a, (1, K // 64)), np.tile(b, (K // 64, 1))
+    if kind == "gauss":
+        return r.standard_normal((M, K)), r.standard_normal((K, N))
+    A = r.laplace(0.0, 1.0, (M, K)) * (1.0 + 4.0 * r.random((1, K)))   # uneven column scales
+    return A, r.laplace(0.0, 1.0, (K, N))
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_plan_parity(td, case):
+    name, M, K, N, L, form, snr, wal, kind, ckind = case
+    log(f"[plan] {name}: M={M} K={K} N={N} L={L} {form} snr={snr} calib={ckind}")
+    A, B = _inputs(kind, M, K, N, zlib.crc32(name.encode()))
+    tabs = _calib(ckind, L, form)
+    cfg = oracle_cfg(L, form, "f64", "snr", snr, wal, 2, 1.0, 127.0)
+    ref = pl.make_plan(A, B, cfg, calib=tabs)
+    calib = td.DeviceCalib(tabs[2].r, {W: tabs[W].s for W in (2, 4)})
+    Ad, Bd = to_dev(A), to_dev(B)
+    desc = td.make_desc(Ad, Bd, L=L, form=form, prec="f64", ctrl="snr", snr_db=snr, w_allowed=wal)
+    plan = td.tdgemm_plan(desc, Ad, Bd, calib)
+    sa, sb, pairs, budget = td.tdgemm_plan_export(plan)
+    nI, nL, nJ, _ = plan.dims
+
+    class _Res:
+        pass
+    res = _Res()
+    res.plan = ref
+    compare_plan(pairs, budget, sa, sb, res, [(i, j) for i in range(nI) for j in range(nJ)])
+    ws = np.bincount(pairs["w"].ravel(), minlength=5)
+    log(f"[plan] {name}: W histogram {ws.tolist()}")
+    if name == "ties_equal_blocks":   # equal D everywhere: pruned pairs are the lowest l
+        w = pairs["w"]
+        for i in range(nI):
+            for j in range(nJ):
+                row = w[i, j]
+                assert all(row[l] <= row[l + 1] for l in range(nL - 1)), row
