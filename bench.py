@@ -4,7 +4,7 @@ One step = the whole hot path on one batch of synthetic input resident in HBM:
 block statistics of A and B, the per-pair plan with inner-kernel pruning, and
 the fused compand / pack / packed-product / unpack / reverse-compand kernel.
 Workload (default): the 4096^3 throughput-distortion sweep point with i.i.d.
-N(0, 1) FP64 inputs, L = 64, symmetric packing, S_kernel = 40 dB for every
+N(0, 1) FP64 inputs, L = 128, symmetric packing, S_kernel = 40 dB for every
 inner kernel, W in {1, 2, 4}. The calibration table s(R, W) is measured on the
 GPU before timing (offline, as the paper prescribes).
 
@@ -51,13 +51,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--dist", default="gaussian", choices=["gaussian", "laplace", "random_range"])
-    ap.add_argument("--L", type=int, default=64)
+    ap.add_argument("--L", type=int, default=128)
     ap.add_argument("--form", default="sym", choices=["sym", "asym"])
     ap.add_argument("--snr", type=float, default=40.0)
     ap.add_argument("--w", default="1,2,4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--cpu-tiles", type=int, default=6)
+    ap.add_argument("--cpu-tiles", type=int, default=16)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run a plain copy kernel of known size (for counter scaling)")
     return ap.parse_args()
@@ -251,8 +251,21 @@ def cpu_baseline(A, B, args):
     from oracle import calibration as cal
     from oracle import pipeline as pl
 
+    from threadpoolctl import threadpool_limits
+
     L = args.L
     n = A.shape[0]
+    with threadpool_limits(limits=1):
+        return _cpu_baseline(A, B, args, L, n)
+
+
+def _cpu_baseline(A, B, args, L, n):
+    import numpy as np
+    import workloads
+    from oracle import blocks as bk
+    from oracle import calibration as cal
+    from oracle import pipeline as pl
+
     ua, ub = workloads.calib_uniforms(L)
     tabs = {W: cal.calibrate(L, W, args.form, "f64", ua, ub, q_max=1 << 18)[0]
             for W in (int(x) for x in args.w.split(",")) if W > 1}
