@@ -78,7 +78,7 @@ typedef struct {
 } tdgemm_desc;
 
 /* Representation-noise table s(R_max, W) of Sec. 4.B (eq. 18), device memory:
- * r[n_r] ascending R values shared by all W; s[3 * n_r] the RMSE in index
+ * r[n_r] strictly ascending R values shared by all W (n_r <= 512); s[3 * n_r] the RMSE in index
  * units for W = 2 (row 0), 3 (row 1) and 4 (row 2); +inf marks an unusable
  * point. Read by the plan's kernels only: keep it alive until the stream has
  * run them. */
