@@ -111,3 +111,39 @@ def test_stats_including_padding(monkeypatch):
         return bk.BlockStats(float(sub.min()), float(sub.max()), exactsum.sum_of_squares(sub), int(sub.size))
     monkeypatch.setattr(bk, "block_stats", bad)
     _fails(tb.test_block_stats_definitions)
+
+
+# --- INT8 / FP8 block-scaled form
+from oracle import precision as pr  # noqa: E402
+from tests import test_oracle_precision as tq  # noqa: E402
+
+
+def test_e4m3_ties_away_from_zero(monkeypatch):
+    def away(v):
+        a = abs(v)
+        if a == 0.0 or a >= 448.0:
+            return orig(v)
+        e = np.frexp(a)[1] - 1
+        step = 2.0 ** -9 if a < 2.0 ** -6 else 2.0 ** (e - 3)
+        return float(np.copysign(min(np.floor(a / step + 0.5) * step, 448.0), v))
+    orig = pr.e4m3_round
+    monkeypatch.setattr(pr, "e4m3_round", away)
+    _fails(tq.test_e4m3_round_nearest_even_brute_force)
+
+
+def test_e4m3_wrong_bias(monkeypatch):
+    orig = pr.e4m3_decode
+    monkeypatch.setattr(pr, "e4m3_decode", lambda c: orig(c) * 2.0)
+    _fails(tq.test_e4m3_code_table)
+
+
+def test_block_scale_from_rms_instead_of_range(monkeypatch):
+    monkeypatch.setattr(pr, "block_scale", lambda st, q: 0.0 if st.amax == 0 else q / (3.0 * st.sigma))
+    _fails(tq.test_integer_blocks_at_full_range_are_exact)
+
+
+def test_int8_truncation_instead_of_rounding(monkeypatch):
+    orig = pr.quantize_block
+    monkeypatch.setattr(pr, "quantize_block",
+                        lambda x, c, fmt: np.trunc(np.asarray(x) * c) if fmt == "i8" else orig(x, c, fmt))
+    _fails(tq.test_int8_snr_matches_prop2, "laplace")
