@@ -46,7 +46,8 @@ typedef enum {
   TDGEMM_E_HIP = -5           /* a HIP runtime call failed */
 } tdgemm_status;
 
-enum { TDGEMM_F64 = 0, TDGEMM_F32 = 1 };                       /* element types */
+enum { TDGEMM_F64 = 0, TDGEMM_F32 = 1,                        /* element types */
+       TDGEMM_I8 = 2, TDGEMM_E4M3 = 3 };                       /* block-scaled forms (prec only) */
 enum { TDGEMM_SYM = 1, TDGEMM_ASYM = 2 };                      /* packing forms */
 enum { TDGEMM_CTRL_SNR = 0, TDGEMM_CTRL_FIXED = 1, TDGEMM_CTRL_SEPARABLE = 2 };
 
@@ -58,7 +59,13 @@ typedef struct {
   int32_t prec;               /* TDGEMM_F64 or TDGEMM_F32: arithmetic of the packed path
                                  (companding, packing, product, unpacking, reverse
                                  companding) and element type of C. F32 packing of
-                                 F64 inputs is not supported. */
+                                 F64 inputs is not supported.
+                                 TDGEMM_I8 / TDGEMM_E4M3: the block-scaled form (Remark 1):
+                                 no packing; the separable rounded operands [[c x]] (INT8,
+                                 |.| <= sep_q <= 127) or E4M3FN(c x) (OCP FP8, sep_q <= 448)
+                                 of every block are multiplied on the INT8 / FP8 matrix
+                                 cores per pair and C (float32) = sum_l r * float(1/(c_A c_B)).
+                                 Requires ctrl = SEPARABLE, fixed_w = 1 and L = 128. */
   int32_t L;                  /* inner-kernel size, eq. (1): 64 or 128 */
   int32_t form;               /* TDGEMM_SYM or TDGEMM_ASYM */
   int32_t ctrl;               /* TDGEMM_CTRL_*:
@@ -129,7 +136,11 @@ tdgemm_status tdgemm_plan(const tdgemm_desc *desc, const void *A, const void *B,
 
 /* Eq. (3): qA[pair] = [[c_a A_il]], qB[pair] = [[c_b B_lj]] per pair (round half
  * to even, in prec; out-of-range elements 0). W = 1 pairs copy the block
- * unrounded. qA, qB: device, n_pairs * L * L elements of prec each. */
+ * unrounded. qA, qB: device, n_pairs * L * L elements of prec each.
+ * Block-scaled forms (prec I8 / E4M3): one byte per element of every block,
+ * shared by all pairs: qA is (nI L) x (nL L) bytes, row m of A with K
+ * contiguous; qB is (nJ L) x (nL L) bytes, column n of B with K contiguous
+ * (B^T); INT8 two's complement or E4M3FN codes; padding is 0. */
 tdgemm_status tdgemm_compand(tdgemm_plan_t plan, const void *A, const void *B,
                              void *qA, void *qB, void *stream);
 
@@ -138,7 +149,8 @@ tdgemm_status tdgemm_compand(tdgemm_plan_t plan, const void *A, const void *B,
  * rows of qB per word (weights z^-i). Asymmetric (eq. 11): pA[pair] is L/W x L
  * with W consecutive rows of qA per word (weights z^i); pB[pair] = qB. Words are
  * evaluated by Horner's rule from the highest slot. W = 1 pairs copy.
- * Buffers: device, n_pairs * L * L elements of prec each. */
+ * Buffers: device, n_pairs * L * L elements of prec each. The block-scaled
+ * forms pack nothing: TDGEMM_E_UNSUPPORTED. */
 tdgemm_status tdgemm_pack(tdgemm_plan_t plan, const void *qA, const void *qB,
                           void *pA, void *pB, void *stream);
 
@@ -148,7 +160,12 @@ tdgemm_status tdgemm_pack(tdgemm_plan_t plan, const void *qA, const void *qB,
  *            n_pairs * L * L elements of prec (L x L symmetric, L/W x L asymmetric).
  * fused = 1: a = A, b = B (as given to tdgemm_plan); out = C. One kernel runs
  *            every stage per pair -- compand, pack, packed product, unpack,
- *            reverse companding -- and accumulates C over l ascending. */
+ *            reverse companding -- and accumulates C over l ascending.
+ * Block-scaled forms: a = qA, b = qB as written by tdgemm_compand. fused = 0:
+ * out = the per-pair products r, n_pairs * L * L elements (int32 for I8, exact;
+ * float32 for E4M3, the matrix cores' float32 sums), row-major per pair.
+ * fused = 1: out = C (float32, ldc), C = sum_l float(r) * float(1/(c_A c_B)),
+ * multiply then add, l ascending. */
 tdgemm_status tdgemm_gemm(tdgemm_plan_t plan, const void *a, const void *b, void *out,
                           int fused, void *stream);
 
@@ -157,7 +174,9 @@ tdgemm_status tdgemm_gemm(tdgemm_plan_t plan, const void *a, const void *b, void
  * C_ij = sum_l r_l * inv_l (W = 1 pairs add their native product).
  * r_int: optional device buffer (NULL to skip) receiving the unpacked integers,
  * n_pairs * L * L elements of prec. C: device output (overwritten), or NULL
- * when only r_int is wanted (at least one of the two must be given). */
+ * when only r_int is wanted (at least one of the two must be given).
+ * Block-scaled forms: Rbar = the per-pair products of tdgemm_gemm(fused = 0);
+ * r_int must be NULL; C (float32) as for fused = 1. */
 tdgemm_status tdgemm_unpack(tdgemm_plan_t plan, const void *Rbar, void *r_int, void *C,
                             void *stream);
 

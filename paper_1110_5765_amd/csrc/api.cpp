@@ -24,14 +24,22 @@ bool is_finite(double x) { return std::isfinite(x); }
 
 bool valid_w(int w) { return w == 1 || w == 2 || w == 4; }
 
+bool block_scaled(int prec) { return prec == TDGEMM_I8 || prec == TDGEMM_E4M3; }
+
 tdgemm_status validate(const tdgemm_desc *d) {
   if (!d) return TDGEMM_E_ARG;
   if (d->M < 0 || d->N < 0 || d->K < 0) return TDGEMM_E_ARG;
   if (d->trans_a != 0 && d->trans_a != 1) return TDGEMM_E_ARG;
   if (d->trans_b != 0 && d->trans_b != 1) return TDGEMM_E_ARG;
   if (d->in_dtype != TDGEMM_F64 && d->in_dtype != TDGEMM_F32) return TDGEMM_E_ARG;
-  if (d->prec != TDGEMM_F64 && d->prec != TDGEMM_F32) return TDGEMM_E_ARG;
+  if (d->prec != TDGEMM_F64 && d->prec != TDGEMM_F32 && !block_scaled(d->prec)) return TDGEMM_E_ARG;
   if (d->prec == TDGEMM_F32 && d->in_dtype == TDGEMM_F64) return TDGEMM_E_UNSUPPORTED;
+  if (block_scaled(d->prec)) {                                   // INT8 / FP8 form
+    if (d->ctrl != TDGEMM_CTRL_SEPARABLE || d->fixed_w != 1) return TDGEMM_E_ARG;
+    if (!(d->sep_q >= 1.0) || !(d->sep_q <= (d->prec == TDGEMM_I8 ? 127.0 : 448.0)))
+      return TDGEMM_E_ARG;
+    if (d->L != 128) return (d->L == 64) ? TDGEMM_E_UNSUPPORTED : TDGEMM_E_ARG;
+  }
   if (d->L != 64 && d->L != 128) return (d->L > 0) ? TDGEMM_E_UNSUPPORTED : TDGEMM_E_ARG;
   if (d->form != TDGEMM_SYM && d->form != TDGEMM_ASYM) return TDGEMM_E_ARG;
   const int64_t need_a = d->trans_a ? d->M : d->K;
@@ -85,6 +93,16 @@ tdg::GemmOperands operands_of(const tdgemm_plan_s *p) {
   g.tb = p->desc.trans_b != 0;
   g.pairs = reinterpret_cast<const tdgemm_pair *>(p->ws + p->ly.off_pairs);
   return g;
+}
+
+tdg::Gemm8Args gemm8_args(const tdgemm_plan_s *p) {
+  tdg::Gemm8Args q;
+  q.qA = nullptr; q.qB = nullptr; q.in = nullptr; q.out = nullptr;
+  q.Kp = p->ly.nL * p->desc.L;
+  q.nI = p->ly.nI; q.nL = p->ly.nL; q.nJ = p->ly.nJ;
+  q.M = p->desc.M; q.N = p->desc.N; q.ldc = p->desc.ldc;
+  q.pairs = reinterpret_cast<const tdgemm_pair *>(p->ws + p->ly.off_pairs);
+  return q;
 }
 
 tdgemm_status hip_status(hipError_t e) { return e == hipSuccess ? TDGEMM_OK : TDGEMM_E_HIP; }
@@ -173,6 +191,7 @@ tdgemm_status tdgemm_plan(const tdgemm_desc *desc, const void *A, const void *B,
         if (desc->ctrl != TDGEMM_CTRL_SNR || (desc->w_allowed & (1u << w))) pl.w_desc[pl.n_opt++] = w;
       if (desc->ctrl != TDGEMM_CTRL_SNR) { pl.n_opt = 1; pl.w_desc[0] = desc->fixed_w; }
       pl.fixed_w = desc->fixed_w;
+      pl.block_scaled = block_scaled(desc->prec) ? 1 : 0;
       pl.fixed_rmax = desc->fixed_rmax;
       pl.sep_q = desc->sep_q;
       pl.u_safe = desc->u_safe;
@@ -230,6 +249,22 @@ tdgemm_status tdgemm_compand(tdgemm_plan_t plan, const void *A, const void *B, v
   if (!plan) return TDGEMM_E_ARG;
   if (plan->ly.n_pairs == 0 || empty_output(plan->desc)) return TDGEMM_OK;
   if (!A || !B || !qA || !qB) return TDGEMM_E_ARG;
+  const tdgemm_desc &d = plan->desc;
+  if (block_scaled(d.prec)) {
+    const Layout &ly = plan->ly;
+    tdg::Quant8Args q;
+    q.A = A; q.B = B;
+    q.M = d.M; q.N = d.N; q.K = d.K; q.lda = d.lda; q.ldb = d.ldb;
+    q.ta = d.trans_a; q.tb = d.trans_b;
+    q.nI = ly.nI; q.nL = ly.nL; q.nJ = ly.nJ;
+    q.Kp = ly.nL * d.L;
+    q.stats_a = reinterpret_cast<const tdgemm_block_stats *>(plan->ws + ly.off_stats_a);
+    q.stats_b = reinterpret_cast<const tdgemm_block_stats *>(plan->ws + ly.off_stats_b);
+    q.q = d.sep_q;
+    q.qA = static_cast<uint8_t *>(qA);
+    q.qB = static_cast<uint8_t *>(qB);
+    return hip_status(tdg::launch_quant8(q, d.in_dtype, d.prec, (hipStream_t)stream));
+  }
   return hip_status(tdg::launch_compand(operands_of(plan), A, B, qA, qB, (hipStream_t)stream));
 }
 
@@ -237,6 +272,7 @@ tdgemm_status tdgemm_pack(tdgemm_plan_t plan, const void *qA, const void *qB, vo
                           void *stream) {
   if (!plan) return TDGEMM_E_ARG;
   if (plan->ly.n_pairs == 0 || empty_output(plan->desc)) return TDGEMM_OK;
+  if (block_scaled(plan->desc.prec)) return TDGEMM_E_UNSUPPORTED;   // nothing is packed
   if (!qA || !qB || !pA || !pB) return TDGEMM_E_ARG;
   return hip_status(tdg::launch_pack(operands_of(plan), qA, qB, pA, pB, (hipStream_t)stream));
 }
@@ -254,6 +290,13 @@ tdgemm_status tdgemm_gemm(tdgemm_plan_t plan, const void *a, const void *b, void
     return hip_status(tdg::launch_fill_zero(out, d.prec, d.M, d.N, d.ldc, (hipStream_t)stream));
   }
   if (!a || !b) return TDGEMM_E_ARG;
+  if (block_scaled(d.prec)) {
+    tdg::Gemm8Args q = gemm8_args(plan);
+    q.qA = static_cast<const uint8_t *>(a);
+    q.qB = static_cast<const uint8_t *>(b);
+    q.out = out;
+    return hip_status(tdg::launch_gemm8(q, d.prec, !fused, (hipStream_t)stream));
+  }
   if (fused) return hip_status(tdg::launch_fused(g, a, b, out, (hipStream_t)stream));
   return hip_status(tdg::launch_packed_product(g, a, b, out, (hipStream_t)stream));
 }
@@ -268,6 +311,13 @@ tdgemm_status tdgemm_unpack(tdgemm_plan_t plan, const void *Rbar, void *r_int, v
     return C ? hip_status(tdg::launch_fill_zero(C, d.prec, d.M, d.N, d.ldc, (hipStream_t)stream))
              : TDGEMM_OK;
   if (!Rbar) return TDGEMM_E_ARG;
+  if (block_scaled(d.prec)) {
+    if (r_int || !C) return TDGEMM_E_ARG;        // the staged products are already integers
+    tdg::Gemm8Args q = gemm8_args(plan);
+    q.in = Rbar;
+    q.out = C;
+    return hip_status(tdg::launch_scale_sum8(q, d.prec, (hipStream_t)stream));
+  }
   return hip_status(tdg::launch_unpack(operands_of(plan), Rbar, r_int, C, (hipStream_t)stream));
 }
 

@@ -35,6 +35,7 @@ struct PlanLaunch {
   int n_opt;
   int w_desc[3];
   int fixed_w;
+  int block_scaled;                    // INT8 / FP8 form: separable records with W = 1
   double fixed_rmax, sep_q, u_safe, snr_lin;
 };
 
@@ -61,6 +62,30 @@ hipError_t launch_unpack(const GemmOperands &g, const void *Rbar, void *r_int, v
 
 // fused path
 hipError_t launch_fused(const GemmOperands &g, const void *A, const void *B, void *C, hipStream_t st);
+
+// Block-scaled INT8 / FP8 form (L = 128)
+struct Quant8Args {
+  const void *A, *B;
+  int64_t M, N, K, lda, ldb;
+  int ta, tb;
+  int64_t nI, nL, nJ;
+  int64_t Kp;                          // nL * 128: row length of qA and qB in bytes
+  const tdgemm_block_stats *stats_a, *stats_b;
+  double q;                            // Q of the block scales c = Q / max|X|
+  uint8_t *qA, *qB;                    // [nI*128][Kp], [nJ*128][Kp]
+};
+
+struct Gemm8Args {
+  const uint8_t *qA, *qB;
+  int64_t Kp, nI, nL, nJ, M, N, ldc;
+  const tdgemm_pair *pairs;
+  const void *in;                      // staged products (k_scale_sum8)
+  void *out;                           // C (float32) or staged products
+};
+
+hipError_t launch_quant8(const Quant8Args &a, int in_dtype, int fmt, hipStream_t st);
+hipError_t launch_gemm8(const Gemm8Args &a, int fmt, bool staged, hipStream_t st);
+hipError_t launch_scale_sum8(const Gemm8Args &a, int fmt, hipStream_t st);
 
 hipError_t launch_fill_zero(void *C, int prec, int64_t M, int64_t N, int64_t ldc, hipStream_t st);
 

@@ -198,6 +198,7 @@ struct PlanArgs {
   int n_opt;                           // allowed W levels, descending in w_desc
   int w_desc[kMaxOpt];
   int fixed_w;
+  int block_scaled;                    // INT8 / FP8 form: separable records with W = 1
   double fixed_rmax, sep_q, u_safe;
   double snr_lin;                      // 10^(-S/10), computed on the host
 };
@@ -417,6 +418,8 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
       else if (zero) o = option_zero(W, a.u_safe);
       else if (k < 0) { o = option_zero(W, a.u_safe); o.d = kDUnavailable; o.s_rep = INFINITY; }
       else o = option_at(W, L_eff, ma, mb, a.calib_r[k], a.calib_s[srow(W) * a.n_r + k], a.u_safe);
+    } else if (a.block_scaled) {
+      o = zero ? option_zero(1, a.u_safe) : option_separable(1, L_eff, ma, mb, a.sep_q, a.u_safe);
     } else {
       const int W = a.fixed_w;
       if (W == 1) o = option_native();
@@ -464,6 +467,7 @@ hipError_t launch_plan(const PlanLaunch &p, hipStream_t st) {
   a.n_opt = p.n_opt;
   for (int v = 0; v < kMaxOpt; ++v) a.w_desc[v] = p.w_desc[v];
   a.fixed_w = p.fixed_w;
+  a.block_scaled = p.block_scaled;
   a.fixed_rmax = p.fixed_rmax;
   a.sep_q = p.sep_q;
   a.u_safe = p.u_safe;

@@ -1,0 +1,300 @@
+// Block-scaled INT8 / FP8 form (Remark 1) on the separable block scales
+// c = Q / max|X| of Sec. 3.A: per-block quantization to byte operands, the
+// per-pair products on the INT8 / FP8 matrix cores, and the float32 reverse
+// companding and l-sum of eqs. (2), (5).
+#include <type_traits>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace tdg {
+
+constexpr int kL8 = 128;          // block size of the precision form
+constexpr int kRow8 = kL8 + 16;   // LDS row stride in bytes (16-byte reads conflict-free)
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Quantization of one value to a byte.
+// INT8: two's complement of [[c x]] (|c x| <= Q <= 127 by construction).
+// E4M3: OCP E4M3FN code of the nearest value, ties to even mantissa, saturating
+// at 448. For |v| >= 2^-6 with v in [2^e, 2^(e+1)), t = [[v 2^(3-e)]] lies in
+// [8, 16] and the code is 8 e + 48 + t (t = 16 carries into the next binade);
+// below 2^-6 the code is [[v 2^9]] (subnormals; 8 is the smallest normal).
+// Both scalings are exact.
+__device__ __forceinline__ uint8_t quant_i8(double v) { return (uint8_t)(int8_t)(int)rint(v); }
+
+__device__ __forceinline__ uint8_t quant_e4m3(double v) {
+  const uint8_t s = signbit(v) ? 0x80 : 0;
+  const double a = fabs(v);
+  int code;
+  if (a < 0.015625) {
+    code = (int)rint(a * 512.0);
+  } else if (a >= 448.0) {
+    code = 126;
+  } else {
+    const int e = ilogb(a);
+    const int t = (int)rint(ldexp(a, 3 - e));
+    code = min(8 * e + 48 + t, 126);
+  }
+  return s | (uint8_t)code;
+}
+
+template <int FMT>
+__device__ __forceinline__ uint8_t quant8(double v) {
+  return FMT == TDGEMM_I8 ? quant_i8(v) : quant_e4m3(v);
+}
+
+// ---------------------------------------------------------------------------
+// One workgroup per block of A (i, l) or of B (l, j). The output tile is 128
+// rows x 128 bytes with K contiguous: rows of A, or columns of B (B^T). The
+// block is read in its stored layout (coalesced), quantized into an LDS tile
+// in output layout, and written out in 16-byte rows.
+template <typename T, int FMT>
+__global__ __launch_bounds__(kThreads) void k_quant8(Quant8Args a) {
+  __shared__ __align__(16) uint8_t tile[kL8][kRow8];
+  const int64_t nbA = a.nI * a.nL;
+  const int64_t b = blockIdx.x;
+  const T *X;
+  int64_t ld, r0, c0;                      // stored block origin
+  int srows, scols;                        // valid stored extents
+  bool direct;                             // stored rows are output rows
+  const tdgemm_block_stats *st;
+  uint8_t *out;
+  if (b < nbA) {                           // A block (i, l): out rows m, K along columns
+    const int64_t i = b / a.nL, l = b - (b / a.nL) * a.nL;
+    const int vm = (int)min<int64_t>(kL8, a.M - i * kL8), vk = (int)min<int64_t>(kL8, a.K - l * kL8);
+    X = static_cast<const T *>(a.A);
+    ld = a.lda;
+    direct = !a.ta;
+    if (direct) { r0 = i * kL8; c0 = l * kL8; srows = vm; scols = vk; }
+    else        { r0 = l * kL8; c0 = i * kL8; srows = vk; scols = vm; }
+    st = &a.stats_a[b];
+    out = a.qA + (i * kL8) * a.Kp + l * kL8;
+  } else {                                 // B block (l, j): out rows n (B^T), K along columns
+    const int64_t bb = b - nbA;
+    const int64_t l = bb / a.nJ, j = bb - (bb / a.nJ) * a.nJ;
+    const int vk = (int)min<int64_t>(kL8, a.K - l * kL8), vn = (int)min<int64_t>(kL8, a.N - j * kL8);
+    X = static_cast<const T *>(a.B);
+    ld = a.ldb;
+    direct = a.tb;
+    if (direct) { r0 = j * kL8; c0 = l * kL8; srows = vn; scols = vk; }
+    else        { r0 = l * kL8; c0 = j * kL8; srows = vk; scols = vn; }
+    st = &a.stats_b[bb];
+    out = a.qB + (j * kL8) * a.Kp + l * kL8;
+  }
+  const BlockMoments mo = moments(*st);
+  const double c = (mo.amax == 0.0) ? 0.0 : a.q / mo.amax;
+  const T *base = X + r0 * ld + c0;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kL8 * kL8; e += kThreads) {
+    const int sr = e / kL8, sc = e - (e / kL8) * kL8;
+    uint8_t v = 0;
+    if (sr < srows && sc < scols) v = quant8<FMT>(c * (double)base[(int64_t)sr * ld + sc]);
+    if (direct) tile[sr][sc] = v;
+    else        tile[sc][sr] = v;
+  }
+  __syncthreads();
+  for (int e = tid; e < kL8 * (kL8 / 16); e += kThreads) {
+    const int r = e / (kL8 / 16), ch = e - (e / (kL8 / 16)) * (kL8 / 16);
+    *reinterpret_cast<v4i *>(out + (int64_t)r * a.Kp + ch * 16) =
+        *reinterpret_cast<const v4i *>(&tile[r][ch * 16]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block-scaled product: one workgroup per inner kernel (i, j), a 128 x 128 tile
+// of C; four wavefronts in 2 x 2, each 64 x 64 = 4 x 4 matrix-core tiles. Per
+// subblock l the byte tiles of A_il and B_lj^T are staged in LDS (double
+// buffered, next l prefetched in registers), multiplied on the matrix cores
+// (INT8 16x16x64 with exact INT32 results; FP8 16x16x128 with FP32 results),
+// and then either written out per pair (STAGED) or added to C as
+// float(r) * float(inv), l ascending.
+template <int FMT, bool STAGED>
+__global__ __launch_bounds__(kThreads) void k_gemm8(Gemm8Args a) {
+  __shared__ __align__(16) uint8_t sa[2][kL8][kRow8];
+  __shared__ __align__(16) uint8_t sb[2][kL8][kRow8];
+  const int64_t tile = blockIdx.x;
+  const int64_t i = tile / a.nJ, j = tile - (tile / a.nJ) * a.nJ;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int g = lane >> 4, li = lane & 15;
+  const uint8_t *gA = a.qA + (i * kL8) * a.Kp;
+  const uint8_t *gB = a.qB + (j * kL8) * a.Kp;
+
+  v4i stage[8];                            // 4 chunks of A, 4 of B (16 bytes each)
+  auto gload = [&](int64_t l) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ch = tid + kThreads * q, r = ch >> 3, c16 = ch & 7;
+      stage[q] = *reinterpret_cast<const v4i *>(gA + (int64_t)r * a.Kp + l * kL8 + c16 * 16);
+      stage[4 + q] = *reinterpret_cast<const v4i *>(gB + (int64_t)r * a.Kp + l * kL8 + c16 * 16);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ch = tid + kThreads * q, r = ch >> 3, c16 = ch & 7;
+      *reinterpret_cast<v4i *>(&sa[buf][r][c16 * 16]) = stage[q];
+      *reinterpret_cast<v4i *>(&sb[buf][r][c16 * 16]) = stage[4 + q];
+    }
+  };
+
+  typedef typename std::conditional<FMT == TDGEMM_I8, v4i, v4f>::type acc_t;
+  acc_t acc[4][4];
+  v4f cacc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      acc[x][y] = acc_t{0, 0, 0, 0};
+      cacc[x][y] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int64_t l = 0; l < a.nL; ++l) {
+    const int buf = (int)(l & 1);
+    if (l + 1 < a.nL) gload(l + 1);
+    if constexpr (FMT == TDGEMM_I8) {
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        v4i fa[4], fb[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+          fa[x] = *reinterpret_cast<const v4i *>(&sa[buf][wr * 64 + x * 16 + li][ks * 64 + g * 16]);
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+          fb[y] = *reinterpret_cast<const v4i *>(&sb[buf][wc * 64 + y * 16 + li][ks * 64 + g * 16]);
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y)
+            acc[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[x], fb[y], acc[x][y], 0, 0, 0);
+      }
+    } else {
+      v8i fa[4], fb[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const uint8_t *p = &sa[buf][wr * 64 + x * 16 + li][g * 32];
+        const v4i lo = *reinterpret_cast<const v4i *>(p), hi = *reinterpret_cast<const v4i *>(p + 16);
+        fa[x] = v8i{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      }
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        const uint8_t *p = &sb[buf][wc * 64 + y * 16 + li][g * 32];
+        const v4i lo = *reinterpret_cast<const v4i *>(p), hi = *reinterpret_cast<const v4i *>(p + 16);
+        fb[y] = v8i{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fa[x], fb[y], acc[x][y], 0, 0,
+                                                                        0, 127, 0, 127);
+    }
+    const int64_t pair = (i * a.nJ + j) * a.nL + l;
+    if constexpr (STAGED) {
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = wr * 64 + x * 16 + 4 * g + r, col = wc * 64 + y * 16 + li;
+            const int64_t o = pair * (kL8 * kL8) + row * kL8 + col;
+            if constexpr (FMT == TDGEMM_I8) static_cast<int32_t *>(a.out)[o] = acc[x][y][r];
+            else                            static_cast<float *>(a.out)[o] = acc[x][y][r];
+          }
+    } else {
+      const float inv = (float)a.pairs[pair].inv;
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) cacc[x][y][r] = cacc[x][y][r] + (float)acc[x][y][r] * inv;
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] = acc_t{0, 0, 0, 0};
+    if (l + 1 < a.nL) sstore(buf ^ 1);
+    __syncthreads();
+  }
+  if constexpr (!STAGED) {
+    float *C = static_cast<float *>(a.out);
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t m = i * kL8 + wr * 64 + x * 16 + 4 * g + r;
+          const int64_t n = j * kL8 + wc * 64 + y * 16 + li;
+          if (m < a.M && n < a.N) C[m * a.ldc + n] = cacc[x][y][r];
+        }
+  }
+}
+
+// C = sum_l float(R_pair) * float(inv_pair), l ascending, from staged products.
+template <int FMT>
+__global__ __launch_bounds__(kThreads) void k_scale_sum8(Gemm8Args a) {
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= a.M * a.N) return;
+  const int64_t m = e / a.N, n = e - (e / a.N) * a.N;
+  const int64_t i = m / kL8, j = n / kL8;
+  const int r = (int)(m - i * kL8), c = (int)(n - j * kL8);
+  float acc = 0.f;
+  for (int64_t l = 0; l < a.nL; ++l) {
+    const int64_t pair = (i * a.nJ + j) * a.nL + l;
+    const int64_t o = pair * (kL8 * kL8) + r * kL8 + c;
+    const float rv = (FMT == TDGEMM_I8) ? (float)static_cast<const int32_t *>(a.in)[o]
+                                        : static_cast<const float *>(a.in)[o];
+    acc = acc + rv * (float)a.pairs[pair].inv;
+  }
+  static_cast<float *>(a.out)[m * a.ldc + n] = acc;
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_quant8(const Quant8Args &a, int in_dtype, int fmt, hipStream_t st) {
+  const int64_t blocks = a.nI * a.nL + a.nL * a.nJ;
+  if (blocks == 0) return hipSuccess;
+  const dim3 grid((unsigned)blocks), blk(kThreads);
+  if (in_dtype == TDGEMM_F64) {
+    if (fmt == TDGEMM_I8) hipLaunchKernelGGL((k_quant8<double, TDGEMM_I8>), grid, blk, 0, st, a);
+    else                  hipLaunchKernelGGL((k_quant8<double, TDGEMM_E4M3>), grid, blk, 0, st, a);
+  } else {
+    if (fmt == TDGEMM_I8) hipLaunchKernelGGL((k_quant8<float, TDGEMM_I8>), grid, blk, 0, st, a);
+    else                  hipLaunchKernelGGL((k_quant8<float, TDGEMM_E4M3>), grid, blk, 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm8(const Gemm8Args &a, int fmt, bool staged, hipStream_t st) {
+  const int64_t tiles = a.nI * a.nJ;
+  if (tiles == 0 || a.nL == 0) return hipSuccess;
+  const dim3 grid((unsigned)tiles), blk(kThreads);
+  if (fmt == TDGEMM_I8) {
+    if (staged) hipLaunchKernelGGL((k_gemm8<TDGEMM_I8, true>), grid, blk, 0, st, a);
+    else        hipLaunchKernelGGL((k_gemm8<TDGEMM_I8, false>), grid, blk, 0, st, a);
+  } else {
+    if (staged) hipLaunchKernelGGL((k_gemm8<TDGEMM_E4M3, true>), grid, blk, 0, st, a);
+    else        hipLaunchKernelGGL((k_gemm8<TDGEMM_E4M3, false>), grid, blk, 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_sum8(const Gemm8Args &a, int fmt, hipStream_t st) {
+  const int64_t n = a.M * a.N;
+  if (n == 0) return hipSuccess;
+  const dim3 grid((unsigned)((n + kThreads - 1) / kThreads)), blk(kThreads);
+  if (fmt == TDGEMM_I8) hipLaunchKernelGGL((k_scale_sum8<TDGEMM_I8>), grid, blk, 0, st, a);
+  else                  hipLaunchKernelGGL((k_scale_sum8<TDGEMM_E4M3>), grid, blk, 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace tdg

@@ -17,13 +17,13 @@ import torch
 
 LIB_PATH = pathlib.Path(__file__).resolve().parent / "libtdgemm.so"
 
-F64, F32 = 0, 1
+F64, F32, I8, E4M3 = 0, 1, 2, 3
 SYM, ASYM = 1, 2
 CTRL_SNR, CTRL_FIXED, CTRL_SEPARABLE = 0, 1, 2
 STATUS = {0: "TDGEMM_OK", -1: "TDGEMM_E_ARG", -2: "TDGEMM_E_UNSUPPORTED",
           -3: "TDGEMM_E_WORKSPACE", -4: "TDGEMM_E_CALIB", -5: "TDGEMM_E_HIP"}
 FORMS = {"sym": SYM, "asym": ASYM}
-PRECS = {"f64": F64, "f32": F32}
+PRECS = {"f64": F64, "f32": F32, "i8": I8, "e4m3": E4M3}
 CTRLS = {"snr": CTRL_SNR, "fixed": CTRL_FIXED, "separable": CTRL_SEPARABLE}
 
 
@@ -208,7 +208,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _LIB is not None:
             _LIB.tdgemm_plan_destroy(h)
             self.handle = None
 
@@ -299,6 +299,34 @@ def tdgemm_status_string(status: int) -> str:
 def slot_elems(plan: Plan) -> int:
     """Elements of a per-pair staging buffer (n_pairs L x L slots)."""
     return plan.dims[3] * plan.desc.L * plan.desc.L
+
+
+def block_scaled_shapes(plan: Plan) -> dict:
+    """Buffer shapes of the block-scaled forms: byte operands qA ((nI L) x (nL L)),
+    qB ((nJ L) x (nL L), B^T) and per-pair products (n_pairs x L x L)."""
+    nI, nL, nJ, n_pairs = plan.dims
+    L = plan.desc.L
+    return {"qA": (nI * L, nL * L), "qB": (nJ * L, nL * L), "products": (n_pairs, L, L)}
+
+
+def block_scaled_matmul(A: torch.Tensor, B: torch.Tensor, fmt: str = "i8", q: float | None = None,
+                        *, out: torch.Tensor | None = None, stream=None):
+    """C (float32) = A B in the INT8 / FP8 block-scaled form: tdgemm_plan (separable
+    block scales), tdgemm_compand (byte operands) and the fused tdgemm_gemm.
+    Returns (C, plan, qA, qB)."""
+    q = (127.0 if fmt == "i8" else 448.0) if q is None else q
+    desc = make_desc(A, B, L=128, prec=fmt, ctrl="separable", fixed_w=1, sep_q=q)
+    plan = tdgemm_plan(desc, A, B, None, stream=stream)
+    sh = block_scaled_shapes(plan)
+    qA = torch.empty(sh["qA"], dtype=torch.uint8, device=A.device)
+    qB = torch.empty(sh["qB"], dtype=torch.uint8, device=A.device)
+    if out is None:
+        out = torch.empty((desc.M, desc.N), dtype=torch.float32, device=A.device)
+    if desc.M > 0 and desc.N > 0 and desc.K > 0:
+        tdgemm_compand(plan, A, B, qA, qB, stream=stream)
+    tdgemm_gemm(plan, qA if qA.numel() else None, qB if qB.numel() else None, out, fused=1,
+                stream=stream)
+    return out, plan, qA, qB
 
 
 def matmul(A: torch.Tensor, B: torch.Tensor, calib: DeviceCalib | None = None, *,
