@@ -10,6 +10,12 @@ GPU before timing (offline, as the paper prescribes).
 
 Prints ONE JSON line on stdout. Metric: effective GFLOP/s = 2 M N K / step
 time, at the stated output SNR against the plain FP64 product.
+
+--workload precision: the 8192^3 Laplace workload of the block-scaled form.
+A step is tdgemm_plan (separable block scales) + tdgemm_compand (INT8 byte
+operands) + the block-scaled tdgemm_gemm; the FP8 form, the packed FP64 form
+at S = 30 and 40 dB and the plain FP64 / FP32 products on the same inputs are
+timed beside it and reported in the same line.
 """
 from __future__ import annotations
 
@@ -49,7 +55,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--workload", default="sweep", choices=["sweep", "precision"])
+    ap.add_argument("--n", type=int, default=None, help="matrix size (4096 sweep, 8192 precision)")
     ap.add_argument("--dist", default="gaussian", choices=["gaussian", "laplace", "random_range"])
     ap.add_argument("--L", type=int, default=128)
     ap.add_argument("--form", default="sym", choices=["sym", "asym"])
@@ -65,27 +72,8 @@ def parse():
 
 def calibrate_gpu(td, torch, L, form, prec, ws):
     """s(R, W) measured on the GPU path (Sec. 4.B protocol), W in ws."""
-    import workloads
-    from numpy import asarray
-    ua, ub = workloads.calib_uniforms(L)
-    dev_a = torch.from_numpy(ua).cuda()
-    dev_b = torch.from_numpy(ub).cuda()
-    q_max = (1 << 18) if prec == "f64" else (1 << 10)
-    qs, k = [], 0
-    while True:
-        q = int(round(2.0 ** (k / 8)))
-        if q > q_max:
-            break
-        if not qs or q != qs[-1]:
-            qs.append(q)
-        k += 1
-    table = {}
-    r0 = None
-    for W in ws:
-        r, m, s = td.tdgemm_calibrate(L, W, form, prec, qs, dev_a, dev_b)
-        r0 = r if r0 is None else r0
-        table[W] = s
-    return td.DeviceCalib(asarray(r0), table), r0, table
+    from paper_1110_5765_amd.calib import device_table
+    return device_table(L, form, prec, tuple(ws))
 
 
 def main():
@@ -107,11 +95,69 @@ def main():
         print(json.dumps({"traffic_probe_bytes_read": n * 8, "bytes_written": n * 8}))
         return
 
+    if args.workload == "precision":
+        return run_precision(args)
+    return run_sweep(args)
+
+
+def timed_steps(torch, step, warmup, steps, phases):
+    """W untimed steps, then exactly K timed steps between device synchronisations.
+    step(ev) records events ev[0..phases] on the current stream between its phases.
+    Returns (ms per step by the host clock, [per-phase mean ms])."""
+    import numpy as np
+    for _ in range(warmup):
+        step(None)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(phases + 1)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ph = [float(np.mean([e[p].elapsed_time(e[p + 1]) for e in evs])) for p in range(phases)]
+    return wall * 1e3 / steps, ph
+
+
+def snr_of(torch, C, ref) -> float:
+    err = C.double() - ref
+    return 10.0 * math.log10(float((ref * ref).sum()) / float((err * err).sum()))
+
+
+def time_plain(torch, Ad, Bd, ref, reps=10):
+    """Plain FP64 and FP32 (on FP32-cast inputs) products on the same GPU."""
+    def time_it(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - s0) / reps
+    n, k = Ad.shape
+    m = Bd.shape[1]
+    flops = 2.0 * n * k * m
+    C64 = torch.empty_like(ref)
+    t64 = time_it(lambda: torch.matmul(Ad, Bd, out=C64))
+    A32, B32 = Ad.float(), Bd.float()
+    C32 = torch.empty((n, m), dtype=torch.float32, device="cuda")
+    t32 = time_it(lambda: torch.matmul(A32, B32, out=C32))
+    snr32 = snr_of(torch, C32, ref)
+    return {"plain_fp64_gflops": round(flops / t64 / 1e9, 1), "plain_fp64_ms": round(t64 * 1e3, 3),
+            "plain_fp32_gflops": round(flops / t32 / 1e9, 1), "plain_fp32_ms": round(t32 * 1e3, 3),
+            "plain_fp32_snr_db": round(snr32, 2)}
+
+
+def run_sweep(args):
+    import numpy as np
+    import torch
+
     import workloads
     from paper_1110_5765_amd import tdgemm as td
 
     ws_allowed = tuple(int(x) for x in args.w.split(","))
-    n = args.n
+    n = args.n or 4096
     log(f"[bench] workload {args.dist} {n}^3 FP64, L={args.L}, {args.form}, S={args.snr} dB, W={ws_allowed}")
     A, B = workloads.sweep(args.dist, n=n)
     Ad = torch.from_numpy(A).cuda()
@@ -127,70 +173,41 @@ def main():
     C = torch.empty((n, n), dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
 
-    def step(ev=None):
+    holder = {}
+
+    def step(ev):
         if ev is not None:
             ev[0].record(stream)
-        plan = td.tdgemm_plan(desc, Ad, Bd, calib, ws)
+        holder["plan"] = td.tdgemm_plan(desc, Ad, Bd, calib, ws)
         if ev is not None:
             ev[1].record(stream)
-        td.tdgemm_gemm(plan, Ad, Bd, C, fused=1)
+        td.tdgemm_gemm(holder["plan"], Ad, Bd, C, fused=1)
         if ev is not None:
             ev[2].record(stream)
-        return plan
 
-    for _ in range(args.warmup):
-        plan = step()
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    for k in range(args.steps):
-        plan = step(evs[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    plan_ms = [e[0].elapsed_time(e[1]) for e in evs]
-    fused_ms = [e[1].elapsed_time(e[2]) for e in evs]
-    step_ms = wall * 1e3 / args.steps
+    step_ms, (plan_avg, fused_avg) = timed_steps(torch, step, args.warmup, args.steps, 2)
+    plan = holder["plan"]
     flops = 2.0 * n * n * n
     gflops = flops / (step_ms * 1e-3) / 1e9
-    log(f"[bench] step {step_ms:.3f} ms (plan+stats {np.mean(plan_ms):.3f} ms, fused {np.mean(fused_ms):.3f} ms)"
+    log(f"[bench] step {step_ms:.3f} ms (plan+stats {plan_avg:.3f} ms, fused {fused_avg:.3f} ms)"
         f" -> {gflops:.1f} effective GFLOP/s")
 
     # accuracy and plan summary (outside the timed region)
     sa, sb, pairs, budget = td.tdgemm_plan_export(plan)
     wh = {int(w): int((pairs["w"] == w).sum()) for w in (1, 2, 4)}
     ref = torch.matmul(Ad, Bd)
-    err = C - ref
-    snr = 10.0 * math.log10(float((ref * ref).sum()) / float((err * err).sum()))
+    snr = snr_of(torch, C, ref)
     L = args.L
     exec_flops = float(sum(2.0 * L * L * L / w * cnt for w, cnt in wh.items()))
-    fused_avg = float(np.mean(fused_ms))
     achieved_tf = exec_flops / (fused_avg * 1e-3) / 1e12
     log(f"[bench] SNR vs FP64 {snr:.2f} dB, W histogram {wh}, executed MFMA {achieved_tf:.2f} TFLOP/s in the fused kernel")
 
     # plain GEMMs on the same GPU
     plain = {}
     if not args.no_plain:
-        def time_it(fn, reps=10):
-            for _ in range(3):
-                fn()
-            torch.cuda.synchronize()
-            s0 = time.perf_counter()
-            for _ in range(reps):
-                fn()
-            torch.cuda.synchronize()
-            return (time.perf_counter() - s0) / reps
-        t64 = time_it(lambda: torch.matmul(Ad, Bd, out=ref))
-        A32, B32 = Ad.float(), Bd.float()
-        C32 = torch.empty((n, n), dtype=torch.float32, device="cuda")
-        t32 = time_it(lambda: torch.matmul(A32, B32, out=C32))
-        e32 = C32.double() - ref
-        snr32 = 10.0 * math.log10(float((ref * ref).sum()) / float((e32 * e32).sum()))
-        plain = {"plain_fp64_gflops": round(flops / t64 / 1e9, 1), "plain_fp64_ms": round(t64 * 1e3, 3),
-                 "plain_fp32_gflops": round(flops / t32 / 1e9, 1), "plain_fp32_ms": round(t32 * 1e3, 3),
-                 "plain_fp32_snr_db": round(snr32, 2)}
+        plain = time_plain(torch, Ad, Bd, ref)
         log(f"[bench] plain FP64 {plain['plain_fp64_gflops']} GFLOP/s, plain FP32 {plain['plain_fp32_gflops']}"
-            f" GFLOP/s at {snr32:.1f} dB")
+            f" GFLOP/s at {plain['plain_fp32_snr_db']} dB")
 
     # traffic from committed counter measurements, if they match the current kernel
     traffic = None
@@ -230,7 +247,7 @@ def main():
         "snr_db": round(snr, 2),
         "pct_fp64_mfma_peak": round(100.0 * gflops / (PEAK_F64_TFLOPS * 1e3), 1),
         "w_histogram": wh,
-        "plan_ms": round(float(np.mean(plan_ms)), 4),
+        "plan_ms": round(plan_avg, 4),
         "fused_ms": round(fused_avg, 4),
         **plain,
         "roofline": {"bound": "mfma", "kernel": "k_fused (FP64 16x16x4 MFMA)",
@@ -239,6 +256,145 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def run_precision(args):
+    """8192^3 Laplace: the block-scaled INT8 form timed as the step, FP8, packed FP64
+    at S = 30 and 40 dB and the plain products beside it."""
+    import torch
+
+    import workloads
+    from paper_1110_5765_amd import tdgemm as td
+
+    n = args.n or 8192
+    L = 128
+    log(f"[bench] precision workload: Laplace(1) {n}^3 FP64, L = {L}, block-scaled INT8 / FP8 "
+        f"vs packed FP64")
+    A, B = workloads.precision(n)
+    Ad = torch.from_numpy(A).cuda()
+    Bd = torch.from_numpy(B).cuda()
+    ref = torch.matmul(Ad, Bd)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    flops = 2.0 * n * n * n
+    forms = {}
+    for fmt, q in (("i8", 127.0), ("e4m3", 448.0)):
+        desc = td.make_desc(Ad, Bd, L=L, prec=fmt, ctrl="separable", fixed_w=1, sep_q=q)
+        ws = torch.empty(td.tdgemm_workspace_size(desc), dtype=torch.uint8, device="cuda")
+        sh = td.block_scaled_shapes(td.tdgemm_plan(desc, Ad, Bd, None, ws))
+        qA = torch.empty(sh["qA"], dtype=torch.uint8, device="cuda")
+        qB = torch.empty(sh["qB"], dtype=torch.uint8, device="cuda")
+        Cf = torch.empty((n, n), dtype=torch.float32, device="cuda")
+
+        def step(ev, desc=desc, ws=ws, qA=qA, qB=qB, Cf=Cf):
+            if ev is not None:
+                ev[0].record(stream)
+            plan = td.tdgemm_plan(desc, Ad, Bd, None, ws)
+            if ev is not None:
+                ev[1].record(stream)
+            td.tdgemm_compand(plan, Ad, Bd, qA, qB)
+            if ev is not None:
+                ev[2].record(stream)
+            td.tdgemm_gemm(plan, qA, qB, Cf, fused=1)
+            if ev is not None:
+                ev[3].record(stream)
+
+        step_ms, (plan_ms, quant_ms, gemm_ms) = timed_steps(torch, step, args.warmup, args.steps, 3)
+        snr = snr_of(torch, Cf, ref)
+        forms[fmt] = {"step_ms": round(step_ms, 4), "gflops": round(flops / step_ms / 1e6, 1),
+                      "snr_db": round(snr, 2), "plan_ms": round(plan_ms, 4),
+                      "quant_ms": round(quant_ms, 4), "gemm_ms": round(gemm_ms, 4), "q": q}
+        log(f"[bench] {fmt}: step {step_ms:.3f} ms (plan {plan_ms:.3f}, quantize {quant_ms:.3f}, "
+            f"product {gemm_ms:.3f}) -> {flops / step_ms / 1e6:.1f} effective GFLOP/s at {snr:.2f} dB")
+        del qA, qB, Cf, ws
+
+    calib, _, _ = calibrate_gpu(td, torch, L, "sym", "f64", [2, 4])
+    packed = {}
+    C64 = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    for S in (30.0, 40.0):
+        desc = td.make_desc(Ad, Bd, L=L, form="sym", ctrl="snr", snr_db=S, w_allowed=(1, 2, 4))
+        ws = torch.empty(td.tdgemm_workspace_size(desc), dtype=torch.uint8, device="cuda")
+        holder = {}
+
+        def step(ev, desc=desc, ws=ws, holder=holder):
+            if ev is not None:
+                ev[0].record(stream)
+            holder["plan"] = td.tdgemm_plan(desc, Ad, Bd, calib, ws)
+            td.tdgemm_gemm(holder["plan"], Ad, Bd, C64, fused=1)
+            if ev is not None:
+                ev[1].record(stream)
+
+        step_ms, _ = timed_steps(torch, step, 1, max(3, args.steps // 4), 1)
+        _, _, pairs, _ = td.tdgemm_plan_export(holder["plan"])
+        wh = {int(w): int((pairs["w"] == w).sum()) for w in (1, 2, 4)}
+        snr = snr_of(torch, C64, ref)
+        packed[f"S{S:g}"] = {"step_ms": round(step_ms, 3), "gflops": round(flops / step_ms / 1e6, 1),
+                             "snr_db": round(snr, 2), "w_histogram": wh}
+        log(f"[bench] packed FP64 sym L={L} S={S:g}: step {step_ms:.3f} ms -> {flops / step_ms / 1e6:.1f} "
+            f"effective GFLOP/s at {snr:.2f} dB, W {wh}")
+        del ws
+    del C64
+    plain = {} if args.no_plain else time_plain(torch, Ad, Bd, ref, reps=5)
+    if plain:
+        log(f"[bench] plain FP64 {plain['plain_fp64_gflops']} GFLOP/s, plain FP32 {plain['plain_fp32_gflops']}"
+            f" GFLOP/s at {plain['plain_fp32_snr_db']} dB")
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = precision_cpu_baseline(A, B)
+        log(f"[bench] oracle on the host: {cpu['value']:.4f} GFLOP/s ({cpu['sample']})")
+    i8 = forms["i8"]
+    tops = flops / (i8["gemm_ms"] * 1e-3) / 1e12
+    out = {
+        "metric": "effective GFLOP/s at fixed output SNR vs plain FP64 GEMM; % of FP64 MFMA peak",
+        "value": i8["gflops"],
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": i8["step_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8",
+        "data": "synthetic",
+        "config": {"workload": f"precision form: C = A B, M = N = K = {n}, A and B i.i.d. Laplace(1) FP64, "
+                               f"L = {L}, separable block scales, INT8 (Q = 127) on the INT8 matrix cores",
+                   "M": n, "N": n, "K": n, "L": L, "parallelism": "single GPU"},
+        "snr_db": i8["snr_db"],
+        "forms": forms,
+        "packed_fp64": packed,
+        **plain,
+        "roofline": {"bound": "mfma", "kernel": "k_gemm8 (INT8 16x16x64 MFMA)", "achieved": round(tops, 1),
+                     "peak": 5000.0, "unit": "TOP/s", "frac": round(tops / 5000.0, 4), "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def precision_cpu_baseline(A, B, corner: int = 1024):
+    """The oracle's INT8 form on the corner A[:c] B[:, :c] (full K), extrapolated:
+    block statistics scale with the blocks of A and B, the rest with the inner kernels."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import blocks as bk
+    from oracle import precision as pr
+
+    n = A.shape[0]
+    Ac, Bc = A[:corner], B[:, :corner]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        pr.run(Ac, Bc, 128, "i8", 127.0, keep_products=False)
+        t1 = time.perf_counter()
+        bk.all_block_stats(Ac, 128)
+        bk.all_block_stats(Bc, 128)
+        t2 = time.perf_counter()
+    t_stats = t2 - t1
+    t_rest = max((t1 - t0) - t_stats, 0.0)
+    f = n / corner
+    total = t_stats * f + t_rest * f * f
+    return {"value": 2.0 * n ** 3 / total / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"INT8 form on the {corner} x {n} by {n} x {corner} corner ({t1 - t0:.1f} s), "
+                      f"statistics scaled by {f:g}, the rest by {f * f:g}"}
 
 
 def cpu_baseline(A, B, args):

@@ -1,0 +1,115 @@
+"""Differentiable linear layer through the throughput-distortion GEMM.
+
+TDLinearFn computes Y = X W (+ b) forward and, backward, dX = dY W^T and
+dW = X^T dY, each product through tdgemm_plan + the fused tdgemm_gemm of the
+library (transposed operands are passed as views, so the library reads them
+in place). Rounding is treated as straight-through: the backward products are
+the packed products of the incoming gradient, not derivatives of the rounding.
+This is how the paper accelerates the back-propagation products of its
+metadata-learning perceptron (Sec. 8.B).
+
+Only argument marshalling happens here; every arithmetic step of the method
+runs in the library's HIP kernels. The bias gradient is a plain column sum.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import torch
+
+from . import tdgemm as td
+
+
+@dataclasses.dataclass
+class TDConfig:
+    """Settings of every product of a layer (see make_desc)."""
+    L: int = 64
+    form: str = "sym"
+    prec: str = "f32"
+    ctrl: str = "snr"
+    snr_db: float = 30.0
+    w_allowed: tuple = (1, 2)
+    fixed_w: int = 2
+    fixed_rmax: float = float(2 ** 20)
+    sep_q: float = 127.0
+    min_dim: int = 128          # products with a smaller M, N or K stay plain (torch)
+
+
+class TDContext:
+    """Calibration table and cached workspaces shared by the products of a model."""
+
+    def __init__(self, cfg: TDConfig, calib: td.DeviceCalib | None):
+        self.cfg = cfg
+        self.calib = calib
+        self._ws: dict = {}
+        self.calls = 0
+        self.plain_calls = 0
+
+    def workspace(self, desc: td.Desc, device) -> torch.Tensor:
+        need = max(td.tdgemm_workspace_size(desc), 256)
+        ws = self._ws.get(device)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(need, dtype=torch.uint8, device=device)
+            self._ws[device] = ws
+        return ws
+
+    def matmul(self, A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
+        """A B through the library (A, B row-major or transposed views)."""
+        c = self.cfg
+        M, K = A.shape
+        N = B.shape[1]
+        if min(M, N, K) < c.min_dim:
+            self.plain_calls += 1
+            return A @ B
+        desc = td.make_desc(A, B, L=c.L, form=c.form, prec=c.prec, ctrl=c.ctrl, snr_db=c.snr_db,
+                            w_allowed=c.w_allowed, fixed_w=c.fixed_w, fixed_rmax=c.fixed_rmax,
+                            sep_q=c.sep_q)
+        ws = self.workspace(desc, A.device)
+        plan = td.tdgemm_plan(desc, A, B, self.calib if c.ctrl == "snr" else None, ws)
+        out = torch.empty((M, N), dtype=td.torch_dtype(desc.prec), device=A.device)
+        td.tdgemm_gemm(plan, A, B, out, fused=1)
+        self.calls += 1
+        return out
+
+
+class TDLinearFn(torch.autograd.Function):
+    """Y = X W + b with packed products forward and backward (straight-through)."""
+
+    @staticmethod
+    def forward(ctx, X, W, b, tdc: TDContext):
+        ctx.tdc = tdc
+        ctx.has_bias = b is not None
+        ctx.save_for_backward(X, W)
+        Y = tdc.matmul(X, W)
+        if b is not None:
+            Y = Y + b
+        return Y
+
+    @staticmethod
+    def backward(ctx, dY):
+        X, W = ctx.saved_tensors
+        tdc = ctx.tdc
+        dY = dY.contiguous()
+        dX = tdc.matmul(dY, W.t()) if ctx.needs_input_grad[0] else None
+        dW = tdc.matmul(X.t(), dY) if ctx.needs_input_grad[1] else None
+        db = dY.sum(0) if ctx.has_bias and ctx.needs_input_grad[2] else None
+        return dX, dW, db, None
+
+
+class TDLinear(torch.nn.Module):
+    """Linear layer y = x W + b (W stored in_features x out_features)."""
+
+    def __init__(self, W: torch.Tensor, b: torch.Tensor | None, tdc: TDContext):
+        super().__init__()
+        self.weight = torch.nn.Parameter(W)
+        self.bias = torch.nn.Parameter(b) if b is not None else None
+        self.tdc = tdc
+
+    def forward(self, x):
+        return TDLinearFn.apply(x, self.weight, self.bias, self.tdc)
+
+
+def calibrate(L: int, form: str, prec: str, ws=(2,), device="cuda") -> td.DeviceCalib:
+    """s(R, W) measured on the GPU path (Sec. 4.B) for the given W values."""
+    from .calib import device_table
+    return device_table(L, form, prec, ws, device)[0]
