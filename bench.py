@@ -11,6 +11,15 @@ GPU before timing (offline, as the paper prescribes).
 Prints ONE JSON line on stdout. Metric: effective GFLOP/s = 2 M N K / step
 time, at the stated output SNR against the plain FP64 product.
 
+--workload mlp: a 512 -> 1024 -> 1024 -> 10 perceptron, batch 4096, trained
+for 200 SGD steps with every large product (forward and backward) through
+the packed FP32 autograd layer, and the same training in plain FP32; ms per
+step and both loss curves are reported.
+
+--workload scatter: X^T X and X P for X = 2000 mean-removed uniform vectors of
+10304 dimensions (float32) and a 10304 x 200 Gaussian P, packed FP64 at
+S = 50, 40 and 20 dB against plain FP64 and FP32.
+
 --workload precision: the 8192^3 Laplace workload of the block-scaled form.
 A step is tdgemm_plan (separable block scales) + tdgemm_compand (INT8 byte
 operands) + the block-scaled tdgemm_gemm; the FP8 form, the packed FP64 form
@@ -55,7 +64,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="sweep", choices=["sweep", "precision"])
+    ap.add_argument("--workload", default="sweep", choices=["sweep", "precision", "mlp", "scatter"])
+    ap.add_argument("--mlp-steps", type=int, default=200)
+    ap.add_argument("--mlp-snr", type=float, default=20.0,
+                    help="S_kernel of the packed FP32 products (W = 2 reaches about 20 dB)")
+    ap.add_argument("--lr", type=float, default=0.1)
     ap.add_argument("--n", type=int, default=None, help="matrix size (4096 sweep, 8192 precision)")
     ap.add_argument("--dist", default="gaussian", choices=["gaussian", "laplace", "random_range"])
     ap.add_argument("--L", type=int, default=128)
@@ -97,6 +110,10 @@ def main():
 
     if args.workload == "precision":
         return run_precision(args)
+    if args.workload == "mlp":
+        return run_mlp(args)
+    if args.workload == "scatter":
+        return run_scatter(args)
     return run_sweep(args)
 
 
@@ -367,6 +384,197 @@ def run_precision(args):
         "roofline": {"bound": "mfma", "kernel": "k_gemm8 (INT8 16x16x64 MFMA)", "achieved": round(tops, 1),
                      "peak": 5000.0, "unit": "TOP/s", "frac": round(tops / 5000.0, 4), "traffic": None},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_mlp(args):
+    """Perceptron training with packed products (autograd layer) against plain FP32."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1110_5765_amd import autograd
+    from paper_1110_5765_amd import tdgemm as td
+    from paper_1110_5765_amd.calib import device_table
+
+    Ws, bs, xs, ys = workloads.mlp()
+    L = args.L if args.L in (64, 128) else 64
+    calib, _, _ = device_table(L, args.form, "f32", (2,))
+    cfg = autograd.TDConfig(L=L, form=args.form, prec="f32", ctrl="snr", snr_db=args.mlp_snr,
+                            w_allowed=(1, 2), min_dim=2 * L)
+    tdc = autograd.TDContext(cfg, calib)
+    X = torch.from_numpy(xs).cuda()
+    Y = torch.from_numpy(ys).cuda()
+    nsteps = args.mlp_steps
+    log(f"[bench] MLP 512-1024-1024-10, batch {xs.shape[1]}, {nsteps} SGD steps (lr {args.lr}), "
+        f"packed FP32 {args.form} L={L} S={args.mlp_snr:g} dB vs plain FP32")
+
+    def make(packed):
+        params = []
+        for W, b in zip(Ws, bs):
+            params.append((torch.from_numpy(W.copy()).cuda().requires_grad_(),
+                           torch.from_numpy(b.copy()).cuda().requires_grad_()))
+        return params
+
+    def forward(params, x, packed):
+        h = x
+        for k, (W, b) in enumerate(params):
+            h = autograd.TDLinearFn.apply(h, W, b, tdc) if packed else h @ W + b
+            if k + 1 < len(params):
+                h = torch.relu(h)
+        return h
+
+    def train(packed):
+        params = make(packed)
+        losses = []
+
+        def one(k):
+            x, y = X[k % X.shape[0]], Y[k % Y.shape[0]]
+            loss = torch.nn.functional.cross_entropy(forward(params, x, packed), y)
+            for W, b in params:
+                W.grad = b.grad = None
+            loss.backward()
+            with torch.no_grad():
+                for W, b in params:
+                    W -= args.lr * W.grad
+                    b -= args.lr * b.grad
+            return loss
+
+        for k in range(3):                       # warm-up on a copy of the start
+            one(k)
+        params = make(packed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ls = [one(k) for k in range(nsteps)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / nsteps
+        losses = [float(v) for v in ls]
+        return ms, losses
+
+    calls0 = tdc.calls
+    ms_p, loss_p = train(True)
+    packed_calls = (tdc.calls - calls0) / (nsteps + 3)
+    ms_q, loss_q = train(False)
+    # distortion of one packed product of the trained shape (forward of layer 2)
+    h = torch.randn(xs.shape[1], 1024, device="cuda")
+    W2 = torch.from_numpy(Ws[1]).cuda()
+    Cp = tdc.matmul(h, W2)
+    _, _, pairs, _ = td.tdgemm_plan_export(tdc.last_plan)
+    wh = {int(w): int((pairs["w"] == w).sum()) for w in (1, 2)}
+    ref = (h.double() @ W2.double())
+    err = Cp.double() - ref
+    snr = 10.0 * math.log10(float((ref * ref).sum()) / float((err * err).sum()))
+    flops = 0.0
+    B = xs.shape[1]
+    sizes = [W.shape for W in Ws]
+    for k, (fi, fo) in enumerate(sizes):
+        flops += 2.0 * B * fi * fo * (3 if k > 0 else 2)        # forward, dW (+ dX past layer 1)
+    gap = max(abs(a - b) for a, b in zip(loss_p, loss_q))
+    log(f"[bench] packed {ms_p:.3f} ms/step ({packed_calls:.0f} packed products per step), plain "
+        f"{ms_q:.3f} ms/step; loss packed {loss_p[0]:.4f} -> {loss_p[-1]:.4f}, plain {loss_q[0]:.4f} -> "
+        f"{loss_q[-1]:.4f}, max gap {gap:.4f}; layer-2 product SNR {snr:.1f} dB, W {wh}")
+    out = {
+        "metric": "effective GFLOP/s at fixed output SNR vs plain FP64 GEMM; % of FP64 MFMA peak",
+        "value": round(flops / ms_p / 1e6, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": nsteps,
+        "warmup": 3,
+        "ms_per_step": round(ms_p, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"MLP 512-1024-1024-10, batch {B}, SGD lr {args.lr}, cross-entropy, packed "
+                               f"FP32 {args.form} products (L = {L}, S = {args.mlp_snr:g} dB, W in [1, 2])",
+                   "steps": nsteps, "parallelism": "single GPU"},
+        "plain_fp32_ms_per_step": round(ms_q, 4),
+        "plain_fp32_gflops": round(flops / ms_q / 1e6, 1),
+        "loss_packed": [round(v, 5) for v in loss_p[:: max(1, nsteps // 20)]] + [round(loss_p[-1], 5)],
+        "loss_plain": [round(v, 5) for v in loss_q[:: max(1, nsteps // 20)]] + [round(loss_q[-1], 5)],
+        "max_loss_gap": round(gap, 5),
+        "product_snr_db": round(snr, 2),
+        "product_w_histogram": wh,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_scatter(args):
+    """Scatter matrix X^T X and projection X P (FP32 inputs, FP64 packing)."""
+    import torch
+
+    import workloads
+    from paper_1110_5765_amd import tdgemm as td
+
+    L = args.L
+    xs, ps = workloads.scatter()
+    X = torch.from_numpy(xs).cuda()
+    P = torch.from_numpy(ps).cuda()
+    calib, _, _ = calibrate_gpu(td, torch, L, args.form, "f64", [2, 4])
+    stream = torch.cuda.current_stream()
+    log(f"[bench] scatter workload: X {tuple(xs.shape)} float32, P {tuple(ps.shape)}; packed FP64 "
+        f"{args.form} L={L}")
+    products = {"XtX": (X.t(), X), "XP": (X, P)}
+    res = {}
+    for name, (A, B) in products.items():
+        M, K = A.shape
+        N = B.shape[1]
+        flops = 2.0 * M * N * K
+        ref = torch.matmul(A.double(), B.double())
+        res[name] = {"M": M, "N": N, "K": K}
+        for S in (50.0, 40.0, 20.0):
+            desc = td.make_desc(A, B, L=L, form=args.form, prec="f64", ctrl="snr", snr_db=S,
+                                w_allowed=(1, 2, 4))
+            ws = torch.empty(td.tdgemm_workspace_size(desc), dtype=torch.uint8, device="cuda")
+            C = torch.empty((M, N), dtype=torch.float64, device="cuda")
+            holder = {}
+
+            def step(ev, desc=desc, ws=ws, C=C, holder=holder, A=A, B=B):
+                if ev is not None:
+                    ev[0].record(stream)
+                holder["plan"] = td.tdgemm_plan(desc, A, B, calib, ws)
+                td.tdgemm_gemm(holder["plan"], A, B, C, fused=1)
+                if ev is not None:
+                    ev[1].record(stream)
+
+            ms, _ = timed_steps(torch, step, 2, max(5, args.steps // 2), 1)
+            _, _, pairs, _ = td.tdgemm_plan_export(holder["plan"])
+            wh = {int(w): int((pairs["w"] == w).sum()) for w in (1, 2, 4)}
+            snr = snr_of(torch, C, ref)
+            res[name][f"S{S:g}"] = {"ms": round(ms, 4), "gflops": round(flops / ms / 1e6, 1),
+                                    "snr_db": round(snr, 2), "w_histogram": wh}
+            log(f"[bench] {name} ({M}x{K} by {K}x{N}) S={S:g}: {ms:.3f} ms -> {flops / ms / 1e6:.1f} "
+                f"effective GFLOP/s at {snr:.2f} dB, W {wh}")
+        A64, B64 = A.double(), B.double()
+        p = time_plain(torch, A64, B64, ref, reps=10)
+        res[name].update(p)
+        log(f"[bench] {name} plain FP64 {p['plain_fp64_gflops']} GFLOP/s, plain FP32 "
+            f"{p['plain_fp32_gflops']} GFLOP/s at {p['plain_fp32_snr_db']} dB")
+    main = res["XtX"]["S40"]
+    out = {
+        "metric": "effective GFLOP/s at fixed output SNR vs plain FP64 GEMM; % of FP64 MFMA peak",
+        "value": main["gflops"],
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": max(5, args.steps // 2),
+        "warmup": 2,
+        "ms_per_step": main["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"scatter matrix X^T X, X = 2000 x 10304 mean-removed uniform float32, packed "
+                               f"FP64 {args.form} L = {L}, S = 40 dB (also X P and S = 50 / 20 dB)",
+                   "parallelism": "single GPU"},
+        "snr_db": main["snr_db"],
+        "products": res,
+        "roofline": None,
+        "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 

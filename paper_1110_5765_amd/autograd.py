@@ -44,6 +44,7 @@ class TDContext:
         self._ws: dict = {}
         self.calls = 0
         self.plain_calls = 0
+        self.last_plan = None
 
     def workspace(self, desc: td.Desc, device) -> torch.Tensor:
         need = max(td.tdgemm_workspace_size(desc), 256)
@@ -69,6 +70,7 @@ class TDContext:
         out = torch.empty((M, N), dtype=td.torch_dtype(desc.prec), device=A.device)
         td.tdgemm_gemm(plan, A, B, out, fused=1)
         self.calls += 1
+        self.last_plan = plan
         return out
 
 

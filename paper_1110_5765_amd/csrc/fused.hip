@@ -134,25 +134,27 @@ struct Fused {
   // plus this thread's fixed offset. With CHECK, out-of-range elements read 0.
   template <bool CHECK, int S>
   __device__ __forceinline__ void load(int64_t k0) {
-    const int lda = (int)pb.lda, ldb = (int)pb.ldb;
     const IT *Ab = TA ? A + k0 * pb.lda + r0 : A + r0 * pb.lda + k0;
     const IT *Bb = TB ? B + c0 * pb.ldb + k0 : B + k0 * pb.ldb + c0;
-    const int krem = CHECK ? (int)min<int64_t>(pb.K - k0, KC) : KC;    // valid inner columns
-    const int mrem = CHECK ? (int)min<int64_t>(pb.M - r0, L) : L;      // valid rows of the tile
+    const int64_t kleft = pb.K - k0, mleft = pb.M - r0;
+    const int krem = CHECK ? (int)(kleft < KC ? kleft : KC) : KC;     // valid inner columns (may be <= 0)
+    const int mrem = CHECK ? (int)(mleft < L ? mleft : L) : L;        // valid rows of the tile
+    // value q of a thread sits at a uniform distance q * step from its first one:
+    // a scalar base per q and one per-thread offset for all of them
+    constexpr bool sym = FORM == TDGEMM_SYM;
+    const int64_t stepA = sym ? (TA ? pb.lda : 1) : (TA ? 1 : pb.lda);
+    const int64_t stepB = TB ? 1 : pb.ldb;
 #pragma unroll
     for (int q = 0; q < VA; ++q) {
       // symmetric: (row a_m, col a_k + q); asymmetric: (row a_m + q, col a_k)
-      const bool sym = FORM == TDGEMM_SYM;
-      const int step = sym ? (TA ? lda : 1) : (TA ? 1 : lda);
       bool ok = true;
       if (CHECK) ok = sym ? (a_row_ok && a_k + q < krem) : (a_m + q < mrem && a_k < krem);
-      ra[S][q] = ok ? (PT)Ab[offA + q * step] : (PT)0;
+      ra[S][q] = ok ? (PT)(Ab + q * stepA)[offA] : (PT)0;
     }
 #pragma unroll
     for (int q = 0; q < VB; ++q) {
-      const int step = TB ? 1 : ldb;
       const bool ok = !CHECK || (b_col_ok && b_k + q < krem);
-      rb[S][q] = ok ? (PT)Bb[offB + q * step] : (PT)0;
+      rb[S][q] = ok ? (PT)(Bb + q * stepB)[offB] : (PT)0;
     }
   }
 
@@ -350,16 +352,27 @@ struct Fused {
     if (kc == NCH - 1) finish_any(ps);
   }
 
-  // walk all pairs of the tile, chunk by chunk
+  // Walk all pairs of the tile, chunk by chunk (chunk g starts at inner index
+  // g KC). A tile inside M and N needs bounds checks only for the chunks that
+  // reach past K: the loop runs unchecked until the first iteration that
+  // prefetches such a chunk, then checked to the end.
   template <bool CHECK>
   __device__ __forceinline__ void run(const tdgemm_pair *prs) {
     const int64_t total = pb.nL * NCH;
+    const int64_t kfull = pb.K / KC;                                  // chunks inside K
+    const int64_t tail = CHECK ? 0 : (kfull < total ? kfull : total);  // first chunk crossing K
     PairState ps = pair_state(prs[0]);
-    load<CHECK, 0>(0);
-    if (total > 1) load<CHECK, 1>(KC);
-    for (int64_t g = 0; g < total; g += 2) {
-      iter<CHECK, 0>(g, total, ps, prs);
-      if (g + 1 < total) iter<CHECK, 1>(g + 1, total, ps, prs);
+    if (tail > 0) load<false, 0>(0); else load<true, 0>(0);
+    if (total > 1) { if (tail > 1) load<false, 1>(KC); else load<true, 1>(KC); }
+    const int64_t g1 = (tail > 2 ? tail - 2 : 0) & ~int64_t(1);   // iterations g < g1 prefetch g + 2 < tail
+    int64_t g = 0;
+    for (; g < g1; g += 2) {
+      iter<false, 0>(g, total, ps, prs);
+      iter<false, 1>(g + 1, total, ps, prs);
+    }
+    for (; g < total; g += 2) {
+      iter<true, 0>(g, total, ps, prs);
+      if (g + 1 < total) iter<true, 1>(g + 1, total, ps, prs);
     }
   }
 
@@ -405,7 +418,7 @@ __global__ __launch_bounds__(4 * L, (L == 64 ? 2 : 1)) void k_fused(GemmOperands
   const int64_t tj = ts / SLABS;
   F f(pb, A, B, sm, ti * L, ts * F::TN);
   const tdgemm_pair *prs = g.pairs + (ti * pb.nJ + tj) * pb.nL;
-  const bool interior = (ti + 1) * L <= pb.M && (ts + 1) * F::TN <= pb.N && pb.K % L == 0;
+  const bool interior = (ti + 1) * L <= pb.M && (ts + 1) * F::TN <= pb.N;
   if (interior) f.template run<false>(prs);
   else f.template run<true>(prs);
   f.write_c(C);
