@@ -17,6 +17,16 @@ constexpr int kWave = 64;              // CDNA wavefront width
 constexpr double kDUnavailable = 1e300;  // D of an option the calibration cannot supply
 constexpr int kMaxR = 512;             // calibration grid points
 
+// Workgroup barrier that orders LDS accesses only: global loads a thread has in
+// flight stay in flight (a plain __syncthreads also waits for them, which
+// would cut a software prefetch short at every barrier). Use it where threads
+// share data through LDS alone.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------------------------
 // Compensated sums. A running sum is a pair (s, c): s the rounded sum, c the
 // accumulated rounding errors (each obtained exactly by TwoSum). s + c rounded

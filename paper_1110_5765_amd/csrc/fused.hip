@@ -76,6 +76,12 @@ struct Fused {
   static constexpr int SA = KC + 1;
   static constexpr int SB = TN + 1;
   static constexpr int NCH = L / KC;      // chunks per pair
+  // Symmetric form, A stored as given: four consecutive threads share a row and
+  // thread i of the four holds columns 4i..4i+3 (and 4i+16..4i+19 when a chunk
+  // has 32 columns), so each 16-byte load of a wavefront covers 64 contiguous
+  // bytes of 16 rows and every packed word (W <= 4) lies in one thread.
+  static constexpr bool A_QUAD = FORM == TDGEMM_SYM && !TA;
+  static constexpr int koffA(int v) { return A_QUAD ? (v % 4) + 16 * (v / 4) : v; }
   static constexpr int PF = 2;            // register sets of raw loads (chunks g+1, g+2)
   typedef typename Mfma<PT>::Acc Acc;
 
@@ -112,7 +118,7 @@ struct Fused {
       // 16 consecutive lanes take 16 consecutive rows, so that their LDS
       // stores hit distinct banks; the 4 lane groups of a wavefront cover the
       // 4 column segments of those rows
-      if (!TA) { a_m = (tid >> 6) * 16 + (tid & 15); a_k = ((tid & 63) >> 4) * VA; }
+      if (!TA) { a_m = tid >> 2;                         a_k = (tid & 3) * 4; }
       else     { a_m = tid % L;                      a_k = (tid / L) * VA; }
     } else {
       if (!TA) { a_k = tid % KC;        a_m = (tid / KC) * VA; }
@@ -148,8 +154,8 @@ struct Fused {
     for (int q = 0; q < VA; ++q) {
       // symmetric: (row a_m, col a_k + q); asymmetric: (row a_m + q, col a_k)
       bool ok = true;
-      if (CHECK) ok = sym ? (a_row_ok && a_k + q < krem) : (a_m + q < mrem && a_k < krem);
-      ra[S][q] = ok ? (PT)(Ab + q * stepA)[offA] : (PT)0;
+      if (CHECK) ok = sym ? (a_row_ok && a_k + koffA(q) < krem) : (a_m + q < mrem && a_k < krem);
+      ra[S][q] = ok ? (PT)(Ab + koffA(q) * stepA)[offA] : (PT)0;
     }
 #pragma unroll
     for (int q = 0; q < VB; ++q) {
@@ -178,7 +184,7 @@ struct Fused {
       PT acc = compand<W>(ra[S][u * W + W - 1], ca);
 #pragma unroll
       for (int s = W - 2; s >= 0; --s) acc = __builtin_fma(acc, z, compand<W>(ra[S][u * W + s], ca));
-      if (FORM == TDGEMM_SYM) sm.a[buf][lds_row_of<PT>(a_m, 1) * SA + a_k / W + u] = acc;
+      if (FORM == TDGEMM_SYM) sm.a[buf][lds_row_of<PT>(a_m, 1) * SA + (a_k + koffA(u * W)) / W] = acc;
       else                    sm.a[buf][lds_row_of<PT>(a_m / W + u, W) * SA + a_k] = acc;
     } else {
       constexpr int u = U - units_a<W>();
@@ -345,7 +351,7 @@ struct Fused {
     if (kc == 0) ps = pair_state(prs[g / NCH]);
     const int buf = (int)(g & 1);
     store_any<S>(buf, ps);
-    __syncthreads();
+    lds_barrier();
     const int64_t g2 = g + 2;
     if (g2 < total) load<CHECK, S>((g2 / NCH) * L + (g2 % NCH) * KC);
     mma_any(buf, ps.w);

@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm8(Gemm8Args a) {
 #pragma unroll
       for (int y = 0; y < 4; ++y) acc[x][y] = acc_t{0, 0, 0, 0};
     if (l + 1 < a.nL) sstore(buf ^ 1);
-    __syncthreads();
+    lds_barrier();
   }
   if constexpr (!STAGED) {
     float *C = static_cast<float *>(a.out);
