@@ -101,7 +101,7 @@ struct Fused {
   int b_n, b_k;           // (col, first row) of B's chunk
   int offA, offB;         // element offsets of (a_m, a_k) and (b_k, b_n) from the chunk corner
   bool a_row_ok, b_col_ok;
-  Acc accR[RB][CB], accC[RB][CB];
+  Acc accR[2][RB][CB], accC[RB][CB];   // accR[P]: packed product of the pairs of parity P
   PT ra[PF][VA], rb[PF][VB];
 
   __device__ __forceinline__ Fused(const Problem &pb_, const IT *A_, const IT *B_, Smem &sm_,
@@ -133,7 +133,9 @@ struct Fused {
 #pragma unroll
     for (int a = 0; a < RB; ++a)
 #pragma unroll
-      for (int b = 0; b < CB; ++b) { accR[a][b] = Mfma<PT>::zero(); accC[a][b] = Mfma<PT>::zero(); }
+      for (int b = 0; b < CB; ++b) {
+        accR[0][a][b] = Mfma<PT>::zero(); accR[1][a][b] = Mfma<PT>::zero(); accC[a][b] = Mfma<PT>::zero();
+      }
   }
 
   // Raw loads of the chunk starting at inner index k0: a uniform base pointer
@@ -212,46 +214,36 @@ struct Fused {
     units<W, S, 0, units_a<W>() + units_b<W>()>(buf, ca, cb, z, zi);
   }
 
-  // The chunk's MFMAs: packed depth KC / W (symmetric) or KC (asymmetric, W = 1).
-  // Wavefront (wr, wc) multiplies packed row blocks of its 64 output rows by its
-  // column blocks, fragments read one k-step ahead. When STORE is set, the
-  // units of the next chunk (register set S, packing W, into buffer nbuf) are
-  // spread over the k-steps, so that the vector ALU compands and packs while
-  // the matrix cores work.
-  template <int W, bool STORE, int S>
-  __device__ __forceinline__ void mma(int buf, int nbuf, PT ca, PT cb, PT z, PT zi) {
+  // The chunk's MFMAs into accumulator set P: packed depth KC / W (symmetric)
+  // or KC (asymmetric, W = 1). Wavefront (wr, wc) multiplies packed row blocks
+  // of its 64 output rows by its column blocks.
+  template <int W, int P>
+  __device__ __forceinline__ void mma(int buf) {
     constexpr bool SYMW = (FORM == TDGEMM_SYM) || W == 1;
     constexpr int NKS = SYMW ? KC / (4 * W) : KC / 4;
     constexpr int RBN = SYMW ? RB : RB / W;
-    constexpr int NU = units_a<W>() + units_b<W>();
     const PT *as = sm.a[buf] + (16 * RBN * wr + lc) * SA + lg;
     const PT *bs = sm.b[buf] + lg * SB + wcol + lc;
-    PT af[2][RBN], bf[2][CB];
-#pragma unroll
-    for (int a = 0; a < RBN; ++a) af[0][a] = as[16 * a * SA];
-#pragma unroll
-    for (int b = 0; b < CB; ++b) bf[0][b] = bs[16 * b];
+    // one fragment set: the reads of k-step ks + 1 go out right after the
+    // MFMAs of ks are issued and return while those execute
     static_for<0, NKS>([&](auto ksc) {
       constexpr int ks = decltype(ksc)::value;
-      constexpr int cur = ks & 1, nxt = cur ^ 1;
-      if constexpr (ks + 1 < NKS) {
+      PT af[RBN], bf[CB];
 #pragma unroll
-        for (int a = 0; a < RBN; ++a) af[nxt][a] = as[16 * a * SA + 4 * (ks + 1)];
+      for (int a = 0; a < RBN; ++a) af[a] = as[16 * a * SA + 4 * ks];
 #pragma unroll
-        for (int b = 0; b < CB; ++b) bf[nxt][b] = bs[4 * (ks + 1) * SB + 16 * b];
-      }
+      for (int b = 0; b < CB; ++b) bf[b] = bs[4 * ks * SB + 16 * b];
 #pragma unroll
       for (int a = 0; a < RBN; ++a)
 #pragma unroll
-        for (int b = 0; b < CB; ++b) accR[a][b] = Mfma<PT>::mma(af[cur][a], bf[cur][b], accR[a][b]);
-      if constexpr (STORE)
-        units<W, S, ks * NU / NKS, (ks + 1) * NU / NKS>(nbuf, ca, cb, z, zi);
+        for (int b = 0; b < CB; ++b)
+          accR[P][a][b] = Mfma<PT>::mma(af[a], bf[b], accR[P][a][b]);
       __builtin_amdgcn_sched_barrier(0);
     });
   }
 
-  // unpack + reverse companding + l-sum
-  template <int W>
+  // unpack + reverse companding + l-sum of the pair held in accumulator set P
+  template <int W, int P>
   __device__ __forceinline__ void finish(PT inv, PT z, PT zi) {
 #pragma unroll
     for (int b = 0; b < CB; ++b) {
@@ -259,13 +251,13 @@ struct Fused {
 #pragma unroll
         for (int a = 0; a < RB; ++a)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) accC[a][b][r] = accC[a][b][r] + accR[a][b][r];
+          for (int r = 0; r < 4; ++r) accC[a][b][r] = accC[a][b][r] + accR[P][a][b][r];
       } else if (FORM == TDGEMM_SYM) {           // eqs. (9)-(10), then eq. (5)
 #pragma unroll
         for (int a = 0; a < RB; ++a)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const PT u = rint(accR[a][b][r]);
+            const PT u = rint(accR[P][a][b][r]);
             const PT t = rint(z * u);
             const PT rr = __builtin_fma(-zi, t, u);     // exact: zi * t is a power-of-two multiple
             accC[a][b][r] = accC[a][b][r] + rr * inv;
@@ -275,7 +267,7 @@ struct Fused {
         for (int a = 0; a < RB / 2; ++a)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const PT v = accR[a][b][r];
+            const PT v = accR[P][a][b][r];
             const PT q0 = rint(v);
             const PT q1 = rint(zi * (v - q0));
             const int ra_ = 2 * a + (r >> 1), rr_ = (r & 1) * 2;
@@ -287,7 +279,7 @@ struct Fused {
         for (int a = 0; a < RB / 4; ++a)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const PT v = accR[a][b][r];
+            const PT v = accR[P][a][b][r];
             const PT q0 = rint(v);
             const PT t1 = zi * (v - q0);
             const PT q1 = rint(t1);
@@ -305,7 +297,7 @@ struct Fused {
 #pragma unroll
     for (int a = 0; a < RB; ++a)
 #pragma unroll
-      for (int b = 0; b < CB; ++b) accR[a][b] = Mfma<PT>::zero();
+      for (int b = 0; b < CB; ++b) accR[P][a][b] = Mfma<PT>::zero();
   }
 
   struct PairState {
@@ -317,7 +309,10 @@ struct Fused {
     PairState ps;
     ps.w = o.w;
     ps.ca = (PT)o.c_a; ps.cb = (PT)o.c_b; ps.inv = (PT)o.inv;
-    ps.z = (PT)ldexp(1.0, -o.p); ps.zi = (PT)ldexp(1.0, o.p);
+    // z = 2^-p and 1/z = 2^p built from exponent bits (integer work, so the
+    // wavefront-uniform state can live in scalar registers); |p| < 1022
+    ps.z = (PT)__builtin_bit_cast(double, (uint64_t)(1023 - o.p) << 52);
+    ps.zi = (PT)__builtin_bit_cast(double, (uint64_t)(1023 + o.p) << 52);
     return ps;
   }
 
@@ -328,58 +323,79 @@ struct Fused {
     else store<4, S>(buf, ps.ca, ps.cb, ps.z, ps.zi);
   }
 
+  template <int P>
   __device__ __forceinline__ void mma_any(int buf, int w) {
-    if (w == 2) mma<2, false, 0>(buf, 0, 0, 0, 0, 0);
-    else if (w == 1) mma<1, false, 0>(buf, 0, 0, 0, 0, 0);
-    else mma<4, false, 0>(buf, 0, 0, 0, 0, 0);
+    if (w == 2) mma<2, P>(buf);
+    else if (w == 1) mma<1, P>(buf);
+    else mma<4, P>(buf);
   }
 
+  template <int P>
   __device__ __forceinline__ void finish_any(const PairState &ps) {
-    if (ps.w == 2) finish<2>(ps.inv, ps.z, ps.zi);
-    else if (ps.w == 1) finish<1>(ps.inv, ps.z, ps.zi);
-    else finish<4>(ps.inv, ps.z, ps.zi);
+    if (ps.w == 2) finish<2, P>(ps.inv, ps.z, ps.zi);
+    else if (ps.w == 1) finish<1, P>(ps.inv, ps.z, ps.zi);
+    else finish<4, P>(ps.inv, ps.z, ps.zi);
   }
 
-  // Chunk g (pair l = g / NCH): compand + pack register set S into LDS buffer
-  // g % 2, barrier, issue the raw loads of chunk g + 2 into set S, run chunk g's
-  // MFMAs and, after the pair's last chunk, unpack. The loads of a chunk are in
-  // flight for two chunks of matrix work before they are used.
-  template <bool CHECK, int S>
-  __device__ __forceinline__ void iter(int64_t g, int64_t total, PairState &ps,
-                                       const tdgemm_pair *prs) {
-    const int kc = (int)(g % NCH);
-    if (kc == 0) ps = pair_state(prs[g / NCH]);
+  // Chunk g of the pair in accumulator set P: compand + pack register set S
+  // into LDS buffer g % 2, barrier, issue the raw loads of chunk g + 2 into set
+  // S (two chunks of matrix work before they are needed), run chunk g's MFMAs.
+  // In the first chunk of a pair the previous pair (set 1 - P) is unpacked
+  // right after these MFMAs are issued, so the vector ALU unpacks while the
+  // matrix cores work.
+  template <bool CHECK, int S, int P>
+  __device__ __forceinline__ void iter(int64_t g, int64_t total, const PairState &ps,
+                                       const PairState &prev, bool finish_prev) {
     const int buf = (int)(g & 1);
     store_any<S>(buf, ps);
     lds_barrier();
     const int64_t g2 = g + 2;
     if (g2 < total) load<CHECK, S>((g2 / NCH) * L + (g2 % NCH) * KC);
-    mma_any(buf, ps.w);
-    if (kc == NCH - 1) finish_any(ps);
+    mma_any<P>(buf, ps.w);
+    if (finish_prev) finish_any<1 - P>(prev);
   }
 
-  // Walk all pairs of the tile, chunk by chunk (chunk g starts at inner index
-  // g KC). A tile inside M and N needs bounds checks only for the chunks that
-  // reach past K: the loop runs unchecked until the first iteration that
-  // prefetches such a chunk, then checked to the end.
+  // All chunks of pair l (NCH is even, so chunk parity restarts with each pair).
+  template <bool CHECK, int P>
+  __device__ __forceinline__ void pair(int64_t l, int64_t total, PairState &ps, PairState &prev,
+                                       const tdgemm_pair *prs) {
+    prev = ps;
+    ps = pair_state(prs[l]);
+    const int64_t g0 = l * NCH;
+    iter<CHECK, 0, P>(g0, total, ps, prev, l > 0);
+    iter<CHECK, 1, P>(g0 + 1, total, ps, prev, false);
+#pragma unroll 1
+    for (int kc = 2; kc < NCH; kc += 2) {
+      iter<CHECK, 0, P>(g0 + kc, total, ps, prev, false);
+      iter<CHECK, 1, P>(g0 + kc + 1, total, ps, prev, false);
+    }
+  }
+
+  // Walk all pairs of the tile. A tile inside M and N needs bounds checks only
+  // for chunks that reach past K (chunk g starts at inner index g KC): pairs
+  // whose prefetches all stay inside K run unchecked, the rest checked.
   template <bool CHECK>
   __device__ __forceinline__ void run(const tdgemm_pair *prs) {
-    const int64_t total = pb.nL * NCH;
+    const int64_t nL = pb.nL, total = nL * NCH;
     const int64_t kfull = pb.K / KC;                                  // chunks inside K
     const int64_t tail = CHECK ? 0 : (kfull < total ? kfull : total);  // first chunk crossing K
-    PairState ps = pair_state(prs[0]);
     if (tail > 0) load<false, 0>(0); else load<true, 0>(0);
     if (total > 1) { if (tail > 1) load<false, 1>(KC); else load<true, 1>(KC); }
-    const int64_t g1 = (tail > 2 ? tail - 2 : 0) & ~int64_t(1);   // iterations g < g1 prefetch g + 2 < tail
-    int64_t g = 0;
-    for (; g < g1; g += 2) {
-      iter<false, 0>(g, total, ps, prs);
-      iter<false, 1>(g + 1, total, ps, prs);
+    // pair l prefetches up to chunk (l + 1) NCH + 1
+    int64_t l1 = tail >= 2 ? (tail - 2) / NCH : 0;
+    l1 -= l1 & 1;
+    PairState ps = pair_state(prs[0]), prev = ps;
+    int64_t l = 0;
+    for (; l < l1; l += 2) {
+      pair<false, 0>(l, total, ps, prev, prs);
+      pair<false, 1>(l + 1, total, ps, prev, prs);
     }
-    for (; g < total; g += 2) {
-      iter<true, 0>(g, total, ps, prs);
-      if (g + 1 < total) iter<true, 1>(g + 1, total, ps, prs);
+    for (; l < nL; l += 2) {
+      pair<true, 0>(l, total, ps, prev, prs);
+      if (l + 1 < nL) pair<true, 1>(l + 1, total, ps, prev, prs);
     }
+    if ((nL - 1) & 1) finish_any<1>(ps);
+    else finish_any<0>(ps);
   }
 
   __device__ __forceinline__ void write_c(PT *__restrict__ C) const {
