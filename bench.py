@@ -20,6 +20,10 @@ step and both loss curves are reported.
 10304 dimensions (float32) and a 10304 x 200 Gaussian P, packed FP64 at
 S = 50, 40 and 20 dB against plain FP64 and FP32.
 
+--workload sweep-table: the whole 4096^3 throughput-distortion sweep, S in
+{60, 52, 44, 36, 28, 20} dB x {sym, asym} x L in {64, 128} x {Gaussian,
+Laplace}, one line with every point (step time, effective GFLOP/s, SNR, W).
+
 --workload precision: the 8192^3 Laplace workload of the block-scaled form.
 A step is tdgemm_plan (separable block scales) + tdgemm_compand (INT8 byte
 operands) + the block-scaled tdgemm_gemm; the FP8 form, the packed FP64 form
@@ -64,7 +68,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="sweep", choices=["sweep", "precision", "mlp", "scatter"])
+    ap.add_argument("--workload", default="sweep", choices=["sweep", "precision", "mlp", "scatter", "sweep-table"])
     ap.add_argument("--mlp-steps", type=int, default=200)
     ap.add_argument("--mlp-snr", type=float, default=20.0,
                     help="S_kernel of the packed FP32 products (W = 2 reaches about 20 dB)")
@@ -114,6 +118,8 @@ def main():
         return run_mlp(args)
     if args.workload == "scatter":
         return run_scatter(args)
+    if args.workload == "sweep-table":
+        return run_sweep_table(args)
     return run_sweep(args)
 
 
@@ -271,6 +277,82 @@ def run_sweep(args):
                      "achieved": round(achieved_tf, 2), "peak": PEAK_F64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved_tf / PEAK_F64_TFLOPS, 4), "traffic": traffic},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_sweep_table(args):
+    """Throughput-distortion sweep at 4096^3: every S, form, L and distribution."""
+    import torch
+
+    import workloads
+    from paper_1110_5765_amd import tdgemm as td
+
+    n = args.n or 4096
+    flops = 2.0 * n ** 3
+    stream = torch.cuda.current_stream()
+    calibs = {}
+    rows = []
+    for dist in ("gaussian", "laplace"):
+        A, B = workloads.sweep(dist, n=n)
+        Ad = torch.from_numpy(A).cuda()
+        Bd = torch.from_numpy(B).cuda()
+        ref = torch.matmul(Ad, Bd)
+        C = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        for L in (64, 128):
+            for form in ("sym", "asym"):
+                if (L, form) not in calibs:
+                    calibs[(L, form)] = calibrate_gpu(td, torch, L, form, "f64", [2, 4])[0]
+                calib = calibs[(L, form)]
+                for S in (60.0, 52.0, 44.0, 36.0, 28.0, 20.0):
+                    desc = td.make_desc(Ad, Bd, L=L, form=form, ctrl="snr", snr_db=S, w_allowed=(1, 2, 4))
+                    ws = torch.empty(td.tdgemm_workspace_size(desc), dtype=torch.uint8, device="cuda")
+                    holder = {}
+
+                    def step(ev, desc=desc, ws=ws, holder=holder):
+                        if ev is not None:
+                            ev[0].record(stream)
+                        holder["plan"] = td.tdgemm_plan(desc, Ad, Bd, calib, ws)
+                        td.tdgemm_gemm(holder["plan"], Ad, Bd, C, fused=1)
+                        if ev is not None:
+                            ev[1].record(stream)
+
+                    ms, _ = timed_steps(torch, step, 2, max(5, args.steps // 2), 1)
+                    _, _, pairs, _ = td.tdgemm_plan_export(holder["plan"])
+                    wh = {int(w): int((pairs["w"] == w).sum()) for w in (1, 2, 4)}
+                    snr = snr_of(torch, C, ref)
+                    rows.append({"dist": dist, "L": L, "form": form, "snr_target_db": S, "ms": round(ms, 4),
+                                 "gflops": round(flops / ms / 1e6, 1), "snr_db": round(snr, 2),
+                                 "w_histogram": wh})
+                    log(f"[bench] {dist:8s} L={L:3d} {form:4s} S={S:4.0f}: {ms:7.3f} ms "
+                        f"{flops / ms / 1e6:9.1f} GFLOP/s  SNR {snr:6.2f} dB  W {wh}")
+                    del ws
+        plain = time_plain(torch, Ad, Bd, ref)
+        log(f"[bench] {dist}: plain FP64 {plain['plain_fp64_gflops']} GFLOP/s, plain FP32 "
+            f"{plain['plain_fp32_gflops']} GFLOP/s at {plain['plain_fp32_snr_db']} dB")
+        rows.append({"dist": dist, "plain": plain})
+        del Ad, Bd, ref, C
+    best = max((r for r in rows if "gflops" in r and r["snr_db"] >= 40.0), key=lambda r: r["gflops"])
+    out = {
+        "metric": "effective GFLOP/s at fixed output SNR vs plain FP64 GEMM; % of FP64 MFMA peak",
+        "value": best["gflops"],
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": max(5, args.steps // 2),
+        "warmup": 2,
+        "ms_per_step": best["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"throughput-distortion sweep, M = N = K = {n}: best point with output SNR >= "
+                               f"40 dB ({best['dist']}, L = {best['L']}, {best['form']}, S = "
+                               f"{best['snr_target_db']:g} dB); all points in 'table'",
+                   "parallelism": "single GPU"},
+        "table": rows,
+        "roofline": None,
+        "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 
