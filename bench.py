@@ -24,6 +24,10 @@ S = 50, 40 and 20 dB against plain FP64 and FP32.
 {60, 52, 44, 36, 28, 20} dB x {sym, asym} x L in {64, 128} x {Gaussian,
 Laplace}, one line with every point (step time, effective GFLOP/s, SNR, W).
 
+--workload fig7: throughput-controlled single-precision GEMM, 4032^3 with the
+generic random-range inputs of Sec. 7, W in {1, 2}, F_kernel from 0 % to
+100 % of the subblock products packed, symmetric and asymmetric forms.
+
 --workload precision: the 8192^3 Laplace workload of the block-scaled form.
 A step is tdgemm_plan (separable block scales) + tdgemm_compand (INT8 byte
 operands) + the block-scaled tdgemm_gemm; the FP8 form, the packed FP64 form
@@ -68,7 +72,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="sweep", choices=["sweep", "precision", "mlp", "scatter", "sweep-table"])
+    ap.add_argument("--workload", default="sweep", choices=["sweep", "precision", "mlp", "scatter", "sweep-table", "fig7"])
     ap.add_argument("--mlp-steps", type=int, default=200)
     ap.add_argument("--mlp-snr", type=float, default=20.0,
                     help="S_kernel of the packed FP32 products (W = 2 reaches about 20 dB)")
@@ -120,6 +124,8 @@ def main():
         return run_scatter(args)
     if args.workload == "sweep-table":
         return run_sweep_table(args)
+    if args.workload == "fig7":
+        return run_fig7(args)
     return run_sweep(args)
 
 
@@ -351,6 +357,78 @@ def run_sweep_table(args):
                                f"{best['snr_target_db']:g} dB); all points in 'table'",
                    "parallelism": "single GPU"},
         "table": rows,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_fig7(args):
+    """Throughput control sweep (F_kernel = 0 .. 100 %), FP32 packing, W in {1, 2}."""
+    import torch
+
+    import workloads
+    from paper_1110_5765_amd import tdgemm as td
+
+    n = args.n or 4032
+    L = 64
+    A = workloads.random_range((n, n), workloads.SEEDS["random_range"][0], L=L).astype("float32")
+    B = workloads.random_range((n, n), workloads.SEEDS["random_range"][1], L=L).astype("float32")
+    Ad = torch.from_numpy(A).cuda()
+    Bd = torch.from_numpy(B).cuda()
+    ref = torch.matmul(Ad.double(), Bd.double())
+    flops = 2.0 * n ** 3
+    stream = torch.cuda.current_stream()
+    C = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    rows = []
+    for form in ("sym", "asym"):
+        calib = calibrate_gpu(td, torch, L, form, "f32", [2])[0]
+        for k in range(11):
+            F = k / 10.0
+            desc = td.make_desc(Ad, Bd, L=L, form=form, prec="f32", ctrl="accel", accel=F, w_allowed=(1, 2))
+            ws = torch.empty(td.tdgemm_workspace_size(desc), dtype=torch.uint8, device="cuda")
+            holder = {}
+
+            def step(ev, desc=desc, ws=ws, holder=holder, calib=calib):
+                if ev is not None:
+                    ev[0].record(stream)
+                holder["plan"] = td.tdgemm_plan(desc, Ad, Bd, calib, ws)
+                td.tdgemm_gemm(holder["plan"], Ad, Bd, C, fused=1)
+                if ev is not None:
+                    ev[1].record(stream)
+
+            ms, _ = timed_steps(torch, step, 2, max(5, args.steps // 2), 1)
+            _, _, pairs, _ = td.tdgemm_plan_export(holder["plan"])
+            packed = float((pairs["w"] == 2).mean())
+            snr = snr_of(torch, C, ref)
+            rows.append({"form": form, "F_kernel": F, "packed_fraction": round(packed, 4), "ms": round(ms, 4),
+                         "gflops": round(flops / ms / 1e6, 1), "snr_db": round(snr, 2)})
+            log(f"[bench] fig7 {form:4s} F={F:3.1f}: packed {packed:6.1%}  {ms:7.3f} ms  "
+                f"{flops / ms / 1e6:9.1f} GFLOP/s  SNR {snr:7.2f} dB")
+    plain = time_plain(torch, Ad.double(), Bd.double(), ref)
+    log(f"[bench] fig7 plain FP64 {plain['plain_fp64_gflops']} GFLOP/s, plain FP32 {plain['plain_fp32_gflops']} "
+        f"GFLOP/s at {plain['plain_fp32_snr_db']} dB")
+    full = {r["form"]: r for r in rows if r["F_kernel"] == 1.0}
+    out = {
+        "metric": "effective GFLOP/s at fixed output SNR vs plain FP64 GEMM; % of FP64 MFMA peak",
+        "value": full["sym"]["gflops"],
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": max(5, args.steps // 2),
+        "warmup": 2,
+        "ms_per_step": full["sym"]["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"throughput control: {n}^3 float32 random-range inputs, FP32 packing, L = {L}, "
+                               f"W in [1, 2], F_kernel = 100 % (sym); all points in 'table'",
+                   "parallelism": "single GPU"},
+        "snr_db": full["sym"]["snr_db"],
+        "snr_gap_sym_minus_asym_db": round(full["sym"]["snr_db"] - full["asym"]["snr_db"], 2),
+        "table": rows,
+        **plain,
         "roofline": None,
         "cpu_baseline": None,
     }

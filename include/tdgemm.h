@@ -49,7 +49,7 @@ typedef enum {
 enum { TDGEMM_F64 = 0, TDGEMM_F32 = 1,                        /* element types */
        TDGEMM_I8 = 2, TDGEMM_E4M3 = 3 };                       /* block-scaled forms (prec only) */
 enum { TDGEMM_SYM = 1, TDGEMM_ASYM = 2 };                      /* packing forms */
-enum { TDGEMM_CTRL_SNR = 0, TDGEMM_CTRL_FIXED = 1, TDGEMM_CTRL_SEPARABLE = 2 };
+enum { TDGEMM_CTRL_SNR = 0, TDGEMM_CTRL_FIXED = 1, TDGEMM_CTRL_SEPARABLE = 2, TDGEMM_CTRL_ACCEL = 3 };
 
 typedef struct {
   int64_t M, N, K;
@@ -73,8 +73,10 @@ typedef struct {
                                  FIXED: every pair at packing fixed_w and range fixed_rmax
                                         with the eq. (26) companders;
                                  SEPARABLE: every pair at packing fixed_w with per-block
-                                        companders c = sep_q / max|block| (Sec. 3.A). */
-  uint32_t w_allowed;         /* SNR mode: bit w set => packing W = w allowed; bit 1
+                                        companders c = sep_q / max|block| (Sec. 3.A);
+                                 ACCEL: the SNR-mode options pruned under the throughput
+                                        constraint F_kernel = accel (Sec. 6). */
+  uint32_t w_allowed;         /* SNR / ACCEL: bit w set => packing W = w allowed; bit 1
                                  (W = 1, native arithmetic) must be set; W in {1, 2, 4} */
   int32_t fixed_w;            /* FIXED / SEPARABLE: W in {1, 2, 4} */
   double snr_db;              /* SNR mode: S_kernel(i, j) in dB for every inner kernel
@@ -82,6 +84,13 @@ typedef struct {
   double fixed_rmax;          /* FIXED: R_max of eqs. (17), (24) */
   double sep_q;               /* SEPARABLE: integer range Q >= 1 of the rounded operands */
   double u_safe;              /* eq. (15) safety term, normally 50 */
+  double accel;               /* ACCEL: F_kernel in [0, 1]. Each inner kernel keeps saving at
+                                 least accel * nL * (1 - 1/W_max) of the W = 1 MFMA work,
+                                 sum_l (1 - 1/W_l); with W in {1, 2} it is the fraction of
+                                 subblock products that stay packed. Starting from W_max
+                                 everywhere, the pair with the largest D (lowest l on ties)
+                                 drops to the next allowed W while the constraint still holds
+                                 afterwards and that D is positive. */
 } tdgemm_desc;
 
 /* Representation-noise table s(R_max, W) of Sec. 4.B (eq. 18), device memory:

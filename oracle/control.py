@@ -142,6 +142,53 @@ def separable_option(W: int, L_eff: int, sa: BlockStats, sb: BlockStats, q: floa
     return PairOption(W, r_safe, c_a, c_b, q_a, q_b, r_safe, p, 1.0 / (c_a * c_b), d, np.nan, 0.0)
 
 
+def saved_units(W: int) -> int:
+    """MFMA work a pair saves at packing W, in units of a quarter of the W = 1
+    product: 4 (1 - 1/W) for W in {1, 2, 4}."""
+    return 4 - 4 // W
+
+
+def accel_target(nl: int, w_max: int, frac: float) -> float:
+    """Required saved work of an inner kernel: the fraction `frac` of what
+    packing every pair at w_max saves."""
+    return frac * nl * saved_units(w_max)
+
+
+def prune_accel(options: list[dict[int, PairOption]], w_desc: list[int], frac: float) -> list[int]:
+    """Sec. 6 pruning under the throughput constraint F_kernel = frac.
+
+    Starting from the maximum packing, the outcome with the highest distortion
+    (lowest l among equals) drops to the next smaller allowed W as long as the
+    inner kernel still saves at least accel_target() units of MFMA work after
+    the drop; it stops before the first drop that would break the constraint
+    and once the highest remaining distortion is 0 (nothing to gain). With
+    W in {1, 2}, frac is the fraction of subblock products that stay packed.
+    """
+    nl = len(options)
+    level = [0] * nl
+    d = [options[l][w_desc[0]].d for l in range(nl)]
+    saved = sum(saved_units(w_desc[0]) for _ in range(nl))
+    target = accel_target(nl, w_desc[0], frac)
+    while True:
+        cand = [l for l in range(nl) if level[l] < len(w_desc) - 1]
+        if not cand:
+            break
+        lstar = cand[0]
+        for l in cand[1:]:
+            if d[l] > d[lstar]:
+                lstar = l
+        if not d[lstar] > 0.0:
+            break
+        w_now, w_next = w_desc[level[lstar]], w_desc[level[lstar] + 1]
+        after = saved - saved_units(w_now) + saved_units(w_next)
+        if after < target:
+            break
+        saved = after
+        level[lstar] += 1
+        d[lstar] = options[lstar][w_desc[level[lstar]]].d
+    return [w_desc[level[l]] for l in range(nl)]
+
+
 def signal_term(L_eff: int, sa: BlockStats, sb: BlockStats) -> float:
     """L_eff s_a^2 s_b^2, one term of the Sec. 6 budget."""
     s_a, s_b = sa.sigma, sb.sigma

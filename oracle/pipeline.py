@@ -13,6 +13,7 @@ C = A B with A (M x K) and B (K x N), following the paper's flow:
 
 Control modes:
 * 'snr'        Sec. 5.B / Sec. 6 distortion control with a calibrated s(R, W).
+* 'accel'      the same options pruned under the throughput constraint F_kernel (Sec. 6).
 * 'fixed'      one (W, R_max) for every pair with the eq. (26) companders.
 * 'separable'  per-block companders c = Q / max|X| with one Q and W.
 
@@ -35,8 +36,9 @@ class Config:
     L: int = 64
     form: str = "sym"            # 'sym' (Sec. 3.B) or 'asym' (Sec. 3.C)
     prec: str = "f64"            # packing arithmetic: 'f64' or 'f32'
-    ctrl: str = "snr"            # 'snr' | 'fixed' | 'separable'
+    ctrl: str = "snr"            # 'snr' | 'accel' | 'fixed' | 'separable'
     snr_db: float = 40.0
+    accel: float = 1.0           # 'accel': required fraction F_kernel of the maximum saved work
     w_allowed: tuple = (1, 2)
     fixed_w: int = 2
     fixed_rmax: float = float(2 ** 20)
@@ -89,7 +91,7 @@ def make_plan(A: np.ndarray, B: np.ndarray, cfg: Config, calib: dict | None = No
             for W in w_desc:
                 if W == 1:
                     o[W] = ct.option_native()
-                elif cfg.ctrl == "snr":
+                elif cfg.ctrl in ("snr", "accel"):
                     o[W] = ct.best_option(W, L_eff, a, b, calib[W], cfg.u_safe)
                 elif cfg.ctrl == "fixed":
                     o[W] = ct.fixed_option(W, L_eff, a, b, cfg.fixed_rmax, cfg.u_safe)
@@ -104,6 +106,8 @@ def make_plan(A: np.ndarray, B: np.ndarray, cfg: Config, calib: dict | None = No
             dk = ct.kernel_budget(terms, cfg.snr_db)
             budget[(i, j)] = dk
             ws = ct.prune(opts_l, w_desc, dk)
+        elif cfg.ctrl == "accel":
+            ws = ct.prune_accel(opts_l, w_desc, cfg.accel)
         else:
             ws = [cfg.fixed_w] * nL
         for l in range(nL):

@@ -49,8 +49,11 @@ tdgemm_status validate(const tdgemm_desc *d) {
     return TDGEMM_E_ARG;
   if (!(d->u_safe > 0.0) || !is_finite(d->u_safe)) return TDGEMM_E_ARG;
   switch (d->ctrl) {
+    case TDGEMM_CTRL_ACCEL:
+      if (!(d->accel >= 0.0 && d->accel <= 1.0)) return TDGEMM_E_ARG;
+      [[fallthrough]];
     case TDGEMM_CTRL_SNR: {
-      if (std::isnan(d->snr_db)) return TDGEMM_E_ARG;
+      if (d->ctrl == TDGEMM_CTRL_SNR && std::isnan(d->snr_db)) return TDGEMM_E_ARG;
       if (!(d->w_allowed & 2u)) return TDGEMM_E_ARG;
       if (d->w_allowed & 8u) return TDGEMM_E_UNSUPPORTED;      // W = 3 needs L divisible by 3
       if (d->w_allowed & ~(2u | 4u | 16u | 8u)) return TDGEMM_E_ARG;
@@ -147,7 +150,8 @@ tdgemm_status tdgemm_plan(const tdgemm_desc *desc, const void *A, const void *B,
   const bool has_work = !empty_output(*desc) && desc->K > 0;
   if (has_work && (!A || !B)) return TDGEMM_E_ARG;
   if (!ws || ws_bytes < ly.total) return TDGEMM_E_WORKSPACE;
-  if (desc->ctrl == TDGEMM_CTRL_SNR) {
+  const bool with_options = desc->ctrl == TDGEMM_CTRL_SNR || desc->ctrl == TDGEMM_CTRL_ACCEL;
+  if (with_options) {
     if (!calib || calib->n_r < 1 || calib->n_r > 512 || !calib->r || !calib->s)
       return TDGEMM_E_CALIB;
   }
@@ -161,7 +165,7 @@ tdgemm_status tdgemm_plan(const tdgemm_desc *desc, const void *A, const void *B,
     auto *sa = reinterpret_cast<tdgemm_block_stats *>(p->ws + ly.off_stats_a);
     auto *sb = reinterpret_cast<tdgemm_block_stats *>(p->ws + ly.off_stats_b);
     auto *tab = reinterpret_cast<tdg::PlanTable *>(p->ws + ly.off_table);
-    const bool snr = desc->ctrl == TDGEMM_CTRL_SNR;
+    const bool snr = with_options;
     tdg::StatsArgs sargs;
     sargs.A = A; sargs.B = B;
     sargs.M = desc->M; sargs.N = desc->N; sargs.K = desc->K;
@@ -188,8 +192,9 @@ tdgemm_status tdgemm_plan(const tdgemm_desc *desc, const void *A, const void *B,
       pl.ctrl = desc->ctrl;
       pl.n_opt = 0;
       for (int w : {4, 2, 1})
-        if (desc->ctrl != TDGEMM_CTRL_SNR || (desc->w_allowed & (1u << w))) pl.w_desc[pl.n_opt++] = w;
-      if (desc->ctrl != TDGEMM_CTRL_SNR) { pl.n_opt = 1; pl.w_desc[0] = desc->fixed_w; }
+        if (!with_options || (desc->w_allowed & (1u << w))) pl.w_desc[pl.n_opt++] = w;
+      if (!with_options) { pl.n_opt = 1; pl.w_desc[0] = desc->fixed_w; }
+      pl.accel = desc->accel;
       pl.fixed_w = desc->fixed_w;
       pl.block_scaled = block_scaled(desc->prec) ? 1 : 0;
       pl.fixed_rmax = desc->fixed_rmax;

@@ -37,6 +37,7 @@ struct PlanLaunch {
   int fixed_w;
   int block_scaled;                    // INT8 / FP8 form: separable records with W = 1
   double fixed_rmax, sep_q, u_safe, snr_lin;
+  double accel;                        // throughput constraint F_kernel (ACCEL control)
 };
 
 // Operands of the packed path (all device pointers).

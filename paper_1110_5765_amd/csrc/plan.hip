@@ -201,6 +201,7 @@ struct PlanArgs {
   int block_scaled;                    // INT8 / FP8 form: separable records with W = 1
   double fixed_rmax, sep_q, u_safe;
   double snr_lin;                      // 10^(-S/10), computed on the host
+  double accel;                        // F_kernel of the throughput constraint
 };
 
 __device__ __forceinline__ int srow(int W) { return W - 2; }   // s table row of W
@@ -219,7 +220,8 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
   __shared__ short sh_idx[3][kMaxR];
   __shared__ int sh_cnt[3];
   __shared__ double sh_ent[kThreads / kWave][kEnt];
-  const bool snr = a.ctrl == TDGEMM_CTRL_SNR;
+  // options over the calibrated grid: distortion (SNR) and throughput (ACCEL) control
+  const bool snr = a.ctrl == TDGEMM_CTRL_SNR || a.ctrl == TDGEMM_CTRL_ACCEL;
   if (snr) {
     if (threadIdx.x < 3) sh_cnt[threadIdx.x] = a.table->cnt[threadIdx.x];
     for (int e = threadIdx.x; e < 3 * kMaxR; e += kThreads) {
@@ -290,7 +292,51 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
 
   double budget = 0.0;
   const int n_ent = a.n_opt - 1;                  // entry levels 0 .. n_opt - 2
-  if (snr && n_ent > 0) {
+  if (a.ctrl == TDGEMM_CTRL_ACCEL && n_ent > 0) {
+    // Throughput constraint: the pair with the largest current D (lowest l among
+    // equals) drops one level while the inner kernel keeps saving at least
+    // accel * nL * units(W_max) units of MFMA work (units(W) = 4 - 4 / W) and that
+    // D is positive.
+    int own = 0;
+#pragma unroll
+    for (int t = 0; t < TT; ++t)
+      if (t < T && lane + (int64_t)kWave * t < pb.nL) own += 4 - 4 / a.w_desc[0];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) own += __shfl_xor(own, off);
+    int saved = own;
+    const double target = (a.accel * (double)pb.nL) * (double)(4 - 4 / a.w_desc[0]);
+    for (;;) {
+      double bd = -INFINITY;
+      int64_t bl = INT64_MAX;
+      int bdelta = 0;
+#pragma unroll
+      for (int t = 0; t < TT; ++t) {
+        const int64_t l = lane + (int64_t)kWave * t;
+        if (t >= T || l >= pb.nL || level[t] >= a.n_opt - 1) continue;
+        double dv = 0.0;
+        int wc = 1, wn = 1;
+#pragma unroll
+        for (int v = 0; v < kMaxOpt; ++v)
+          if (level[t] == v) { dv = dopt[v][t]; wc = a.w_desc[v]; wn = a.w_desc[v + 1 < kMaxOpt ? v + 1 : v]; }
+        if (dv > bd || (dv == bd && l < bl)) { bd = dv; bl = l; bdelta = (4 - 4 / wc) - (4 - 4 / wn); }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double od = __shfl_xor(bd, off);
+        const int64_t ol = __shfl_xor(bl, off);
+        const int odl = __shfl_xor(bdelta, off);
+        if (od > bd || (od == bd && ol < bl)) { bd = od; bl = ol; bdelta = odl; }
+      }
+      if (bl == INT64_MAX || !(bd > 0.0)) break;
+      if ((double)(saved - bdelta) < target) break;
+      saved -= bdelta;
+      if ((bl & (kWave - 1)) == lane) {
+        const int tt = (int)(bl / kWave);
+#pragma unroll
+        for (int t = 0; t < TT; ++t) if (t == tt) level[t] += 1;
+      }
+    }
+  } else if (a.ctrl == TDGEMM_CTRL_SNR && n_ent > 0) {
     budget = a.snr_lin * wave_csum(sig);
     // does every pair's D decrease strictly along its entries (and weakly to the floor)?
     bool mono = true;
@@ -394,7 +440,7 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
         }
       }
     }
-  } else if (snr) {
+  } else if (a.ctrl == TDGEMM_CTRL_SNR) {
     budget = a.snr_lin * wave_csum(sig);
   }
 
@@ -472,6 +518,7 @@ hipError_t launch_plan(const PlanLaunch &p, hipStream_t st) {
   a.sep_q = p.sep_q;
   a.u_safe = p.u_safe;
   a.snr_lin = p.snr_lin;
+  a.accel = p.accel;
   const int64_t tiles = p.pb.nI * p.pb.nJ;
   const unsigned blocks = (unsigned)((tiles + (kThreads / kWave) - 1) / (kThreads / kWave));
   const int64_t T = (p.pb.nL + kWave - 1) / kWave;

@@ -19,12 +19,12 @@ LIB_PATH = pathlib.Path(__file__).resolve().parent / "libtdgemm.so"
 
 F64, F32, I8, E4M3 = 0, 1, 2, 3
 SYM, ASYM = 1, 2
-CTRL_SNR, CTRL_FIXED, CTRL_SEPARABLE = 0, 1, 2
+CTRL_SNR, CTRL_FIXED, CTRL_SEPARABLE, CTRL_ACCEL = 0, 1, 2, 3
 STATUS = {0: "TDGEMM_OK", -1: "TDGEMM_E_ARG", -2: "TDGEMM_E_UNSUPPORTED",
           -3: "TDGEMM_E_WORKSPACE", -4: "TDGEMM_E_CALIB", -5: "TDGEMM_E_HIP"}
 FORMS = {"sym": SYM, "asym": ASYM}
 PRECS = {"f64": F64, "f32": F32, "i8": I8, "e4m3": E4M3}
-CTRLS = {"snr": CTRL_SNR, "fixed": CTRL_FIXED, "separable": CTRL_SEPARABLE}
+CTRLS = {"snr": CTRL_SNR, "fixed": CTRL_FIXED, "separable": CTRL_SEPARABLE, "accel": CTRL_ACCEL}
 
 
 class Desc(ctypes.Structure):
@@ -35,7 +35,7 @@ class Desc(ctypes.Structure):
                 ("form", ctypes.c_int32), ("ctrl", ctypes.c_int32), ("w_allowed", ctypes.c_uint32),
                 ("fixed_w", ctypes.c_int32), ("snr_db", ctypes.c_double),
                 ("fixed_rmax", ctypes.c_double), ("sep_q", ctypes.c_double),
-                ("u_safe", ctypes.c_double)]
+                ("u_safe", ctypes.c_double), ("accel", ctypes.c_double)]
 
 
 class Calib(ctypes.Structure):
@@ -147,7 +147,8 @@ def w_mask(ws) -> int:
 def make_desc(A: torch.Tensor, B: torch.Tensor, *, L: int = 64, form: str = "sym",
               prec: str | None = None, ctrl: str = "snr", snr_db: float = 40.0,
               w_allowed=(1, 2, 4), fixed_w: int = 2, fixed_rmax: float = float(2 ** 20),
-              sep_q: float = 127.0, u_safe: float = 50.0, ldc: int | None = None) -> Desc:
+              sep_q: float = 127.0, u_safe: float = 50.0, accel: float = 1.0,
+              ldc: int | None = None) -> Desc:
     M, K = A.shape
     K2, N = B.shape
     if K != K2:
@@ -172,6 +173,7 @@ def make_desc(A: torch.Tensor, B: torch.Tensor, *, L: int = 64, form: str = "sym
     d.fixed_rmax = fixed_rmax
     d.sep_q = sep_q
     d.u_safe = u_safe
+    d.accel = accel
     return d
 
 
@@ -333,7 +335,8 @@ def matmul(A: torch.Tensor, B: torch.Tensor, calib: DeviceCalib | None = None, *
            out: torch.Tensor | None = None, stream=None, **kw) -> tuple[torch.Tensor, Plan]:
     """C = A B through tdgemm_plan + the fused tdgemm_gemm. Keyword arguments as make_desc."""
     desc = make_desc(A, B, **kw)
-    plan = tdgemm_plan(desc, A, B, calib, stream=stream)
+    plan = tdgemm_plan(desc, A, B, calib if desc.ctrl in (CTRL_SNR, CTRL_ACCEL) else None,
+                       stream=stream)
     if out is None:
         out = torch.empty((desc.M, desc.N), dtype=torch_dtype(desc.prec), device=A.device)
     tdgemm_gemm(plan, A, B, out, fused=1, stream=stream)

@@ -56,13 +56,13 @@ def test_struct_layout_matches_binding(binding, tmp_path):
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "tdgemm.h"\n'
                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n",'
                    'sizeof(tdgemm_desc), sizeof(tdgemm_pair), sizeof(tdgemm_block_stats),'
-                   'sizeof(tdgemm_calib), offsetof(tdgemm_desc, snr_db), offsetof(tdgemm_desc, u_safe),'
+                   'sizeof(tdgemm_calib), offsetof(tdgemm_desc, snr_db), offsetof(tdgemm_desc, accel),'
                    'offsetof(tdgemm_pair, w), offsetof(tdgemm_desc, w_allowed));return 0;}\n')
     exe = tmp_path / "sizes"
     subprocess.run(["gcc", "-std=c99", f"-I{ROOT / 'include'}", str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [ctypes.sizeof(binding.Desc), ctypes.sizeof(binding.Pair), ctypes.sizeof(binding.BlockStats),
-            ctypes.sizeof(binding.Calib), binding.Desc.snr_db.offset, binding.Desc.u_safe.offset,
+            ctypes.sizeof(binding.Calib), binding.Desc.snr_db.offset, binding.Desc.accel.offset,
             binding.Pair.w.offset, binding.Desc.w_allowed.offset]
     assert got == want
     assert binding.PAIR_DTYPE.itemsize == ctypes.sizeof(binding.Pair)

@@ -88,3 +88,46 @@ def test_plan_parity(td, case):
             for j in range(nJ):
                 row = w[i, j]
                 assert all(row[l] <= row[l + 1] for l in range(nL - 1)), row
+
+
+ACCEL_CASES = [
+    # name, M, K, N, L, form, frac, w_allowed, inputs
+    ("accel_w2_f0", 128, 384, 128, 64, "sym", 0.0, (1, 2), "laplace"),
+    ("accel_w2_f03", 192, 640, 128, 64, "sym", 0.3, (1, 2), "gauss"),
+    ("accel_w2_f05_asym", 128, 512, 192, 64, "asym", 0.5, (1, 2), "laplace"),
+    ("accel_w2_f1", 128, 384, 128, 64, "sym", 1.0, (1, 2), "gauss"),
+    ("accel_w24_f06", 256, 1024, 64, 64, "sym", 0.6, (1, 2, 4), "laplace"),
+    ("accel_L128_many_l", 128, 128 * 70, 128, 128, "sym", 0.45, (1, 2, 4), "gauss"),
+    ("accel_ties", 128, 384, 128, 64, "sym", 0.5, (1, 2), "tiled"),
+]
+
+
+@pytest.mark.parametrize("case", ACCEL_CASES, ids=[c[0] for c in ACCEL_CASES])
+def test_accel_plan_parity(td, case):
+    """Throughput-constrained pruning (F_kernel): records bit-exact to the oracle."""
+    name, M, K, N, L, form, frac, wal, kind = case
+    log(f"[plan] {name}: M={M} K={K} N={N} L={L} {form} F={frac} W={wal}")
+    A, B = _inputs(kind, M, K, N, zlib.crc32(name.encode()))
+    tabs = _calib("std", L, form)
+    cfg = pl.Config(L=L, form=form, prec="f64", ctrl="accel", accel=frac, w_allowed=tuple(wal))
+    ref = pl.make_plan(A, B, cfg, calib=tabs)
+    calib = td.DeviceCalib(tabs[2].r, {W: tabs[W].s for W in (2, 4)})
+    Ad, Bd = to_dev(A), to_dev(B)
+    desc = td.make_desc(Ad, Bd, L=L, form=form, prec="f64", ctrl="accel", accel=frac, w_allowed=wal)
+    plan = td.tdgemm_plan(desc, Ad, Bd, calib)
+    sa, sb, pairs, budget = td.tdgemm_plan_export(plan)
+    nI, nL, nJ, _ = plan.dims
+
+    class _Res:
+        pass
+    res = _Res()
+    res.plan = ref
+    compare_plan(pairs, budget, sa, sb, res, [(i, j) for i in range(nI) for j in range(nJ)])
+    ws = np.bincount(pairs["w"].ravel(), minlength=5)
+    log(f"[plan] {name}: W histogram {ws.tolist()}")
+    if name == "accel_w2_f05_asym":          # the product too
+        C = torch.empty((M, N), dtype=torch.float64, device="cuda")
+        td.tdgemm_gemm(plan, Ad, Bd, C, fused=1)
+        Cref = pl.run(A, B, cfg, calib=tabs, plan=ref).C
+        got = C.cpu().numpy()
+        assert float(np.linalg.norm(got - Cref) / np.linalg.norm(Cref)) <= 1e-12

@@ -155,3 +155,52 @@ def test_symmetric_beats_asymmetric_at_full_w2_single_precision():
         assert all(o.W == 2 for o in res.plan.chosen.values())
         out[form] = pl.snr_db(res.C, A @ B)
     assert out["sym"] > out["asym"]
+
+
+# --- throughput-constrained pruning (F_kernel)
+
+def test_prune_accel_two_levels_is_the_cheapest_fraction():
+    """W in {1, 2}: the greedy keeps the ceil(F nL) pairs of smallest D at W = 2 (lowest l
+    first among equals); brute force over all subsets of that size confirms it minimises
+    the sum of D under the constraint."""
+    rng = np.random.default_rng(21)
+    for trial in range(200):
+        n = int(rng.integers(1, 9))
+        d2 = rng.exponential(1.0, n) + 0.01
+        if trial % 4 == 0:
+            d2[rng.integers(0, n)] = d2[0]
+        frac = float(rng.choice([0.0, 0.1, 0.25, 0.5, 0.7, 1.0, rng.uniform()]))
+        opts = [{2: _opt(2, float(d)), 1: _opt(1, 0.0)} for d in d2]
+        got = ct.prune_accel(opts, [2, 1], frac)
+        need = math.ceil(frac * n - 1e-12)
+        assert sum(w == 2 for w in got) == need
+        best = min(sum(d2[l] for l in keep) for keep in itertools.combinations(range(n), need))
+        assert math.isclose(sum(d2[l] for l in range(n) if got[l] == 2), best, rel_tol=0, abs_tol=0)
+
+
+def test_prune_accel_extremes_and_invariants():
+    rng = np.random.default_rng(22)
+    for trial in range(150):
+        n = int(rng.integers(1, 6))
+        d2 = rng.exponential(1.0, n) + 0.01
+        d4 = d2 + rng.exponential(3.0, n)
+        opts = [{4: _opt(4, float(d4[l])), 2: _opt(2, float(d2[l])), 1: _opt(1, 0.0)} for l in range(n)]
+        assert ct.prune_accel(opts, [4, 2, 1], 1.0) == [4] * n
+        assert ct.prune_accel(opts, [4, 2, 1], 0.0) == [1] * n
+        frac = float(rng.uniform())
+        w = ct.prune_accel(opts, [4, 2, 1], frac)
+        saved = sum(ct.saved_units(x) for x in w)
+        target = ct.accel_target(n, 4, frac)
+        assert saved >= target
+        # the next greedy move (highest current D that can still drop) would break the target
+        cur = [opts[l][w[l]].d for l in range(n)]
+        cand = [l for l in range(n) if w[l] != 1]
+        if cand:
+            l = max(cand, key=lambda x: (cur[x], -x))
+            nxt = {4: 2, 2: 1}[w[l]]
+            assert saved - ct.saved_units(w[l]) + ct.saved_units(nxt) < target
+
+
+def test_prune_accel_keeps_zero_distortion_pairs():
+    opts = [{2: _opt(2, 0.0), 1: _opt(1, 0.0)}, {2: _opt(2, 1.0), 1: _opt(1, 0.0)}]
+    assert ct.prune_accel(opts, [2, 1], 0.0) == [2, 1]      # nothing to gain from the first

@@ -1,6 +1,8 @@
 """The pins catch plausible mistakes: each test plants one mistake in the oracle
 (on the CPU, by monkeypatching a function for the duration of the test) and
 checks that the corresponding pin then fails."""
+import math
+
 import numpy as np
 import pytest
 
@@ -147,3 +149,14 @@ def test_int8_truncation_instead_of_rounding(monkeypatch):
     monkeypatch.setattr(pr, "quantize_block",
                         lambda x, c, fmt: np.trunc(np.asarray(x) * c) if fmt == "i8" else orig(x, c, fmt))
     _fails(tq.test_int8_snr_matches_prop2, "laplace")
+
+
+def test_prune_accel_removes_smallest(monkeypatch):
+    def wrong(options, w_desc, frac):
+        nl = len(options)
+        order = sorted(range(nl), key=lambda l: (options[l][w_desc[0]].d, l))   # smallest first
+        need = math.ceil(frac * nl - 1e-12)
+        keep = set(order[len(order) - need:]) if need else set()
+        return [w_desc[0] if l in keep else w_desc[-1] for l in range(nl)]
+    monkeypatch.setattr(ct, "prune_accel", wrong)
+    _fails(tc.test_prune_accel_two_levels_is_the_cheapest_fraction)
