@@ -349,8 +349,10 @@ struct Fused {
     const int buf = (int)(g & 1);
     store_any<S>(buf, ps);
     lds_barrier();
-    const int64_t g2 = g + 2;
-    if (g2 < total) load<CHECK, S>((g2 / NCH) * L + (g2 % NCH) * KC);
+    // always issued (the last chunk again past the end), so that the number of
+    // loads in flight is the same on every path and waits count exactly
+    const int64_t g2 = g + 2 < total ? g + 2 : total - 1;
+    load<CHECK, S>((g2 / NCH) * L + (g2 % NCH) * KC);
     mma_any<P>(buf, ps.w);
     if (finish_prev) finish_any<1 - P>(prev);
   }
