@@ -40,7 +40,7 @@ extern "C" {
 typedef enum {
   TDGEMM_OK = 0,
   TDGEMM_E_ARG = -1,          /* invalid argument or shape */
-  TDGEMM_E_UNSUPPORTED = -2,  /* valid but not implemented (e.g. W = 3, L = 96) */
+  TDGEMM_E_UNSUPPORTED = -2,  /* valid but not implemented (e.g. W = 4 at L = 96) */
   TDGEMM_E_WORKSPACE = -3,    /* workspace missing or too small */
   TDGEMM_E_CALIB = -4,        /* calibration table missing or malformed */
   TDGEMM_E_HIP = -5           /* a HIP runtime call failed */
@@ -66,7 +66,9 @@ typedef struct {
                                  of every block are multiplied on the INT8 / FP8 matrix
                                  cores per pair and C (float32) = sum_l r * float(1/(c_A c_B)).
                                  Requires ctrl = SEPARABLE, fixed_w = 1 and L = 128. */
-  int32_t L;                  /* inner-kernel size, eq. (1): 64 or 128 */
+  int32_t L;                  /* inner-kernel size, eq. (1): 64, 96 or 128. The packings W
+                                 must divide L: {1, 2, 4} at L = 64 and 128, {1, 2, 3} at
+                                 L = 96 (W = 4 at L = 96: TDGEMM_E_UNSUPPORTED) */
   int32_t form;               /* TDGEMM_SYM or TDGEMM_ASYM */
   int32_t ctrl;               /* TDGEMM_CTRL_*:
                                  SNR: Sec. 5.B / Sec. 6 control to snr_db per inner kernel;
@@ -77,8 +79,9 @@ typedef struct {
                                  ACCEL: the SNR-mode options pruned under the throughput
                                         constraint F_kernel = accel (Sec. 6). */
   uint32_t w_allowed;         /* SNR / ACCEL: bit w set => packing W = w allowed; bit 1
-                                 (W = 1, native arithmetic) must be set; W in {1, 2, 4} */
-  int32_t fixed_w;            /* FIXED / SEPARABLE: W in {1, 2, 4} */
+                                 (W = 1, native arithmetic) must be set; W in {1, 2, 4}, or
+                                 {1, 2, 3} at L = 96 */
+  int32_t fixed_w;            /* FIXED / SEPARABLE: W in {1, 2, 4}, or {1, 2, 3} at L = 96 */
   double snr_db;              /* SNR mode: S_kernel(i, j) in dB for every inner kernel
                                  (Sec. 6); +inf requests native precision everywhere */
   double fixed_rmax;          /* FIXED: R_max of eqs. (17), (24) */
@@ -203,8 +206,8 @@ tdgemm_status tdgemm_plan_dims(tdgemm_plan_t plan, int64_t *nI, int64_t *nL, int
 
 tdgemm_status tdgemm_plan_destroy(tdgemm_plan_t plan);
 
-/* Representation-noise measurement of Sec. 4.B (eq. 18) on the GPU path:
- * for each integer range q[t] (host, n_q values >= 1) the inputs are integers
+/* Representation-noise measurement of Sec. 4.B (eq. 18) on the GPU path, at
+ * packing W > 1 (a packing L supports, see tdgemm_desc.L): for each integer range q[t] (host, n_q values >= 1) the inputs are integers
  * uniform on {-q..q}, obtained from the uniform [0, 1) draws u_a, u_b (device,
  * n_inst * L * L each) as floor(u (2q + 1)) - q; c_A = c_B = 1; R_max = L q^2;
  * z from eq. (15). The packed product of each instance is unpacked and compared

@@ -143,9 +143,11 @@ def separable_option(W: int, L_eff: int, sa: BlockStats, sb: BlockStats, q: floa
 
 
 def saved_units(W: int) -> int:
-    """MFMA work a pair saves at packing W, in units of a quarter of the W = 1
-    product: 4 (1 - 1/W) for W in {1, 2, 4}."""
-    return 4 - 4 // W
+    """MFMA work a pair saves at packing W, in twelfths of the W = 1 product:
+    12 (1 - 1/W), an integer for every W in {1, 2, 3, 4}."""
+    if 12 % W:
+        raise ValueError(f"W = {W} does not divide 12")
+    return 12 - 12 // W
 
 
 def accel_target(nl: int, w_max: int, frac: float) -> float:

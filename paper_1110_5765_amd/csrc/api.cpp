@@ -22,7 +22,17 @@ using tdg::Problem;
 
 bool is_finite(double x) { return std::isfinite(x); }
 
-bool valid_w(int w) { return w == 1 || w == 2 || w == 4; }
+bool valid_l(int L) { return L == 64 || L == 96 || L == 128; }
+
+// Packings a block size supports: W divides L (eq. 1) and the kernels keep
+// whole MFMA steps: {1, 2, 4} at L = 64 and 128, {1, 2, 3} at L = 96.
+// E_ARG for a W outside {1, ..., 4} or one that does not divide L, and
+// E_UNSUPPORTED for W = 4 at L = 96.
+tdgemm_status check_w(int w, int L) {
+  if (w < 1 || w > 4 || L % w != 0) return TDGEMM_E_ARG;
+  if (L == 96 && w == 4) return TDGEMM_E_UNSUPPORTED;
+  return TDGEMM_OK;
+}
 
 bool block_scaled(int prec) { return prec == TDGEMM_I8 || prec == TDGEMM_E4M3; }
 
@@ -38,9 +48,9 @@ tdgemm_status validate(const tdgemm_desc *d) {
     if (d->ctrl != TDGEMM_CTRL_SEPARABLE || d->fixed_w != 1) return TDGEMM_E_ARG;
     if (!(d->sep_q >= 1.0) || !(d->sep_q <= (d->prec == TDGEMM_I8 ? 127.0 : 448.0)))
       return TDGEMM_E_ARG;
-    if (d->L != 128) return (d->L == 64) ? TDGEMM_E_UNSUPPORTED : TDGEMM_E_ARG;
+    if (d->L != 128) return valid_l(d->L) ? TDGEMM_E_UNSUPPORTED : TDGEMM_E_ARG;
   }
-  if (d->L != 64 && d->L != 128) return (d->L > 0) ? TDGEMM_E_UNSUPPORTED : TDGEMM_E_ARG;
+  if (!valid_l(d->L)) return (d->L > 0) ? TDGEMM_E_UNSUPPORTED : TDGEMM_E_ARG;
   if (d->form != TDGEMM_SYM && d->form != TDGEMM_ASYM) return TDGEMM_E_ARG;
   const int64_t need_a = d->trans_a ? d->M : d->K;
   const int64_t need_b = d->trans_b ? d->K : d->N;
@@ -55,20 +65,26 @@ tdgemm_status validate(const tdgemm_desc *d) {
     case TDGEMM_CTRL_SNR: {
       if (d->ctrl == TDGEMM_CTRL_SNR && std::isnan(d->snr_db)) return TDGEMM_E_ARG;
       if (!(d->w_allowed & 2u)) return TDGEMM_E_ARG;
-      if (d->w_allowed & 8u) return TDGEMM_E_UNSUPPORTED;      // W = 3 needs L divisible by 3
-      if (d->w_allowed & ~(2u | 4u | 16u | 8u)) return TDGEMM_E_ARG;
+      if (d->w_allowed & ~(2u | 4u | 8u | 16u)) return TDGEMM_E_ARG;
+      for (int w = 2; w <= 4; ++w) {
+        if (!(d->w_allowed & (1u << w))) continue;
+        const tdgemm_status sw = check_w(w, d->L);
+        if (sw != TDGEMM_OK) return sw;
+      }
       break;
     }
-    case TDGEMM_CTRL_FIXED:
-      if (d->fixed_w == 3) return TDGEMM_E_UNSUPPORTED;
-      if (!valid_w(d->fixed_w)) return TDGEMM_E_ARG;
+    case TDGEMM_CTRL_FIXED: {
+      const tdgemm_status sw = check_w(d->fixed_w, d->L);
+      if (sw != TDGEMM_OK) return sw;
       if (!(d->fixed_rmax > 0.0) || !is_finite(d->fixed_rmax)) return TDGEMM_E_ARG;
       break;
-    case TDGEMM_CTRL_SEPARABLE:
-      if (d->fixed_w == 3) return TDGEMM_E_UNSUPPORTED;
-      if (!valid_w(d->fixed_w)) return TDGEMM_E_ARG;
+    }
+    case TDGEMM_CTRL_SEPARABLE: {
+      const tdgemm_status sw = check_w(d->fixed_w, d->L);
+      if (sw != TDGEMM_OK) return sw;
       if (!(d->sep_q >= 1.0) || !is_finite(d->sep_q)) return TDGEMM_E_ARG;
       break;
+    }
     default:
       return TDGEMM_E_ARG;
   }
@@ -191,7 +207,7 @@ tdgemm_status tdgemm_plan(const tdgemm_desc *desc, const void *A, const void *B,
       pl.n_r = calib ? calib->n_r : 0;
       pl.ctrl = desc->ctrl;
       pl.n_opt = 0;
-      for (int w : {4, 2, 1})
+      for (int w : {4, 3, 2, 1})
         if (!with_options || (desc->w_allowed & (1u << w))) pl.w_desc[pl.n_opt++] = w;
       if (!with_options) { pl.n_opt = 1; pl.w_desc[0] = desc->fixed_w; }
       pl.accel = desc->accel;
@@ -327,7 +343,7 @@ tdgemm_status tdgemm_unpack(tdgemm_plan_t plan, const void *Rbar, void *r_int, v
 }
 
 size_t tdgemm_calibrate_workspace_size(int32_t L, int32_t n_inst) {
-  if ((L != 64 && L != 128) || n_inst < 1) return 0;
+  if (!valid_l(L) || n_inst < 1) return 0;
   const size_t slot = tdg::align256(sizeof(double) * (size_t)n_inst * L * L);
   // qA qB pA pB Rbar r_int refA refB refR, records x2, moments
   return 9 * slot + 2 * tdg::align256(sizeof(tdgemm_pair) * (size_t)n_inst) + 256;
@@ -337,9 +353,10 @@ tdgemm_status tdgemm_calibrate(int32_t L, int32_t W, int32_t form, int32_t prec,
                                int32_t n_q, const double *u_a, const double *u_b, int32_t n_inst,
                                double u_safe, double *r_out, double *m_out, double *s_out, void *ws,
                                size_t ws_bytes, void *stream) {
-  if (L != 64 && L != 128) return L > 0 ? TDGEMM_E_UNSUPPORTED : TDGEMM_E_ARG;
-  if (W == 3) return TDGEMM_E_UNSUPPORTED;
-  if (W != 2 && W != 4) return TDGEMM_E_ARG;
+  if (!valid_l(L)) return L > 0 ? TDGEMM_E_UNSUPPORTED : TDGEMM_E_ARG;
+  if (W < 2) return TDGEMM_E_ARG;
+  const tdgemm_status sw = check_w(W, L);
+  if (sw != TDGEMM_OK) return sw;
   if (form != TDGEMM_SYM && form != TDGEMM_ASYM) return TDGEMM_E_ARG;
   if (prec != TDGEMM_F64 && prec != TDGEMM_F32) return TDGEMM_E_ARG;
   if (!q || n_q < 1 || !u_a || !u_b || n_inst < 1 || !r_out || !m_out || !s_out) return TDGEMM_E_ARG;

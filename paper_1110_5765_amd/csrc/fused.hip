@@ -54,6 +54,18 @@ __device__ __forceinline__ void owner_of_packed_row(int ml, int W, int &g, int &
   else             { g = ml & 3;         r = ml >> 2; }
 }
 
+// L = 96: lane group g of a wavefront owns the 24 consecutive tile rows
+// 24 g .. 24 g + 23 (slot (a, g, r) holds row 24 g + 4 a + r), so the W
+// consecutive rows of an asymmetric word (W in {1, 2, 3}) stay in one lane.
+// Packed row mb (W = 1: tile row) goes to the MFMA position that yields its
+// first slot: k = mb mod (24 / W) counts the words of lane group g.
+template <typename PT, int W>
+__device__ __forceinline__ int lds_row_of96(int mb) {
+  constexpr int per = 24 / W;
+  const int g = mb / per, k = mb - g * per;
+  return 16 * (k >> 2) + mfma_pos<PT>(g, k & 3);
+}
+
 template <typename PT>
 __device__ __forceinline__ int lds_row_of(int m, int W) {
   int g, r;
@@ -63,14 +75,20 @@ __device__ __forceinline__ int lds_row_of(int m, int W) {
 
 template <typename IT, typename PT, int L, int FORM, bool TA, bool TB>
 struct Fused {
-  static constexpr int TN = 64;           // output columns per workgroup
-  static constexpr int NT = 4 * L;        // threads: L / 16 wavefronts as (L / 64) x 4
-  static constexpr int WC = 4;            // wavefront columns, 16 output columns each
-  static constexpr int RB = 4;            // 16-row blocks per wavefront (64 rows)
+  static constexpr bool L96 = L == 96;
+  static constexpr int TN = L96 ? 96 : 64;  // output columns per workgroup
+  static constexpr int NT = 4 * L;        // threads: L / 16 wavefronts
+  static constexpr int WC = L96 ? 6 : 4;  // wavefront columns, 16 output columns each
+  static constexpr int RB = L96 ? 6 : 4;  // 16-row blocks per wavefront
   static constexpr int CB = 1;            // 16-column blocks per wavefront
-  static constexpr int KC = (L == 64) ? 16 : 32;  // raw inner columns per chunk
-  static constexpr int VA = KC * L / NT;  // raw A values per thread per chunk (8)
-  static constexpr int VB = KC * TN / NT; // raw B values per thread per chunk (8 or 4)
+  static constexpr int KC = (L == 64) ? 16 : (L96 ? 24 : 32);  // raw inner columns per chunk
+  static constexpr int VA = KC * L / NT;  // raw A values per thread per chunk
+  static constexpr int VB = KC * TN / NT; // raw B values per thread per chunk
+  static constexpr int WMAX = L96 ? 3 : 4;  // packings: {1, 2, WMAX}
+  // packed accumulator sets: two let a pair's unpack overlap the next pair's
+  // MFMAs; with one (L = 96, six row blocks per wavefront) the unpack runs
+  // before them
+  static constexpr int NACC = L96 ? 1 : 2;
   // LDS row strides in elements: with an odd A stride the 16 rows read by one
   // group of 16 lanes fall on distinct bank pairs.
   static constexpr int SA = KC + 1;
@@ -80,10 +98,18 @@ struct Fused {
   // thread i of the four holds columns 4i..4i+3 (and 4i+16..4i+19 when a chunk
   // has 32 columns), so each 16-byte load of a wavefront covers 64 contiguous
   // bytes of 16 rows and every packed word (W <= 4) lies in one thread.
+  // (L = 96: thread i of the four holds columns 6i..6i+5.)
   static constexpr bool A_QUAD = FORM == TDGEMM_SYM && !TA;
-  static constexpr int koffA(int v) { return A_QUAD ? (v % 4) + 16 * (v / 4) : v; }
+  static constexpr bool A_SPLIT = A_QUAD && VA == 8;
+  static constexpr int koffA(int v) { return A_SPLIT ? (v % 4) + 16 * (v / 4) : v; }
   static constexpr int PF = 2;            // register sets of raw loads (chunks g+1, g+2)
   typedef typename Mfma<PT>::Acc Acc;
+  static_assert(VA * NT == KC * L && VB * NT == KC * TN, "loads must cover a chunk");
+  static_assert(KC % (4 * WMAX) == 0 && KC % 8 == 0, "packed chunk depth: whole k-steps");
+  static_assert(VA % WMAX == 0 && VA % 2 == 0 && VB % WMAX == 0 && VB % 2 == 0,
+                "a thread's raw values form whole packed words");
+  static_assert(RB % WMAX == 0 && RB % 2 == 0, "asymmetric words: whole row blocks");
+  static_assert(NT == 64 * WC * (L / (16 * RB)), "wavefront grid covers the tile");
 
   struct Smem {
     PT a[2][L * SA];
@@ -101,7 +127,7 @@ struct Fused {
   int b_n, b_k;           // (col, first row) of B's chunk
   int offA, offB;         // element offsets of (a_m, a_k) and (b_k, b_n) from the chunk corner
   bool a_row_ok, b_col_ok;
-  Acc accR[2][RB][CB], accC[RB][CB];   // accR[P]: packed product of the pairs of parity P
+  Acc accR[NACC][RB][CB], accC[RB][CB];   // accR[P]: packed product of the pairs of parity P
   PT ra[PF][VA], rb[PF][VB];
 
   __device__ __forceinline__ Fused(const Problem &pb_, const IT *A_, const IT *B_, Smem &sm_,
@@ -112,13 +138,13 @@ struct Fused {
     lg = lane >> 4;
     lc = lane & 15;
     wr = (tid >> 6) / WC;
-    wrow = wr * 64;
+    wrow = wr * 16 * RB;
     wcol = ((tid >> 6) % WC) * 16;
     if (FORM == TDGEMM_SYM) {
       // 16 consecutive lanes take 16 consecutive rows, so that their LDS
       // stores hit distinct banks; the 4 lane groups of a wavefront cover the
       // 4 column segments of those rows
-      if (!TA) { a_m = tid >> 2;                         a_k = (tid & 3) * 4; }
+      if (!TA) { a_m = tid >> 2;                         a_k = (tid & 3) * (A_SPLIT ? 4 : VA); }
       else     { a_m = tid % L;                      a_k = (tid / L) * VA; }
     } else {
       if (!TA) { a_k = tid % KC;        a_m = (tid / KC) * VA; }
@@ -134,7 +160,7 @@ struct Fused {
     for (int a = 0; a < RB; ++a)
 #pragma unroll
       for (int b = 0; b < CB; ++b) {
-        accR[0][a][b] = Mfma<PT>::zero(); accR[1][a][b] = Mfma<PT>::zero(); accC[a][b] = Mfma<PT>::zero();
+        accR[0][a][b] = Mfma<PT>::zero(); accR[NACC - 1][a][b] = Mfma<PT>::zero(); accC[a][b] = Mfma<PT>::zero();
       }
   }
 
@@ -179,6 +205,13 @@ struct Fused {
   template <int W>
   static constexpr int units_b() { return (FORM == TDGEMM_SYM && W > 1) ? VB / W : VB; }
 
+  // LDS row of packed A row mb (W = 1: tile row)
+  template <int W>
+  __device__ __forceinline__ static int a_row(int mb) {
+    if constexpr (L96) return lds_row_of96<PT, W>(mb);
+    else return lds_row_of<PT>(mb, W);
+  }
+
   template <int W, int S, int U>
   __device__ __forceinline__ void unit(int buf, PT ca, PT cb, PT z, PT zi) {
     if (U < units_a<W>()) {
@@ -186,8 +219,8 @@ struct Fused {
       PT acc = compand<W>(ra[S][u * W + W - 1], ca);
 #pragma unroll
       for (int s = W - 2; s >= 0; --s) acc = __builtin_fma(acc, z, compand<W>(ra[S][u * W + s], ca));
-      if (FORM == TDGEMM_SYM) sm.a[buf][lds_row_of<PT>(a_m, 1) * SA + (a_k + koffA(u * W)) / W] = acc;
-      else                    sm.a[buf][lds_row_of<PT>(a_m / W + u, W) * SA + a_k] = acc;
+      if (FORM == TDGEMM_SYM) sm.a[buf][a_row<1>(a_m) * SA + (a_k + koffA(u * W)) / W] = acc;
+      else                    sm.a[buf][a_row<W>(a_m / W + u) * SA + a_k] = acc;
     } else {
       constexpr int u = U - units_a<W>();
       if (FORM == TDGEMM_SYM && W > 1) {
@@ -262,6 +295,22 @@ struct Fused {
             const PT rr = __builtin_fma(-zi, t, u);     // exact: zi * t is a power-of-two multiple
             accC[a][b][r] = accC[a][b][r] + rr * inv;
           }
+      } else if (L96) {                          // eqs. (13)-(14): W rows per word
+        // word k = 4 a + r of a lane group yields its rows W k + s, in the
+        // slots (W k + s) / 4, register (W k + s) mod 4
+#pragma unroll
+        for (int a = 0; a < RB / W; ++a)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            PT t = accR[P][a][b][r];
+#pragma unroll
+            for (int sl = 0; sl < W; ++sl) {
+              const PT q = rint(t);
+              const int o = W * (4 * a + r) + sl;
+              accC[o >> 2][b][o & 3] = accC[o >> 2][b][o & 3] + q * inv;
+              if (sl + 1 < W) t = zi * (t - q);
+            }
+          }
       } else if (W == 2) {                       // eqs. (13)-(14), two rows per word
 #pragma unroll
         for (int a = 0; a < RB / 2; ++a)
@@ -320,21 +369,21 @@ struct Fused {
   __device__ __forceinline__ void store_any(int buf, const PairState &ps) {
     if (ps.w == 2) store<2, S>(buf, ps.ca, ps.cb, ps.z, ps.zi);
     else if (ps.w == 1) store<1, S>(buf, ps.ca, ps.cb, ps.z, ps.zi);
-    else store<4, S>(buf, ps.ca, ps.cb, ps.z, ps.zi);
+    else store<WMAX, S>(buf, ps.ca, ps.cb, ps.z, ps.zi);
   }
 
   template <int P>
   __device__ __forceinline__ void mma_any(int buf, int w) {
     if (w == 2) mma<2, P>(buf);
     else if (w == 1) mma<1, P>(buf);
-    else mma<4, P>(buf);
+    else mma<WMAX, P>(buf);
   }
 
   template <int P>
   __device__ __forceinline__ void finish_any(const PairState &ps) {
     if (ps.w == 2) finish<2, P>(ps.inv, ps.z, ps.zi);
     else if (ps.w == 1) finish<1, P>(ps.inv, ps.z, ps.zi);
-    else finish<4, P>(ps.inv, ps.z, ps.zi);
+    else finish<WMAX, P>(ps.inv, ps.z, ps.zi);
   }
 
   // Chunk g of the pair in accumulator set P: compand + pack register set S
@@ -353,8 +402,9 @@ struct Fused {
     // loads in flight is the same on every path and waits count exactly
     const int64_t g2 = g + 2 < total ? g + 2 : total - 1;
     load<CHECK, S>((g2 / NCH) * L + (g2 % NCH) * KC);
+    if (NACC == 1 && finish_prev) finish_any<0>(prev);
     mma_any<P>(buf, ps.w);
-    if (finish_prev) finish_any<1 - P>(prev);
+    if (NACC == 2 && finish_prev) finish_any<NACC - 1 - P>(prev);
   }
 
   // All chunks of pair l (NCH is even, so chunk parity restarts with each pair).
@@ -388,15 +438,16 @@ struct Fused {
     l1 -= l1 & 1;
     PairState ps = pair_state(prs[0]), prev = ps;
     int64_t l = 0;
+    constexpr int P1 = NACC - 1;             // set of the odd pairs
     for (; l < l1; l += 2) {
       pair<false, 0>(l, total, ps, prev, prs);
-      pair<false, 1>(l + 1, total, ps, prev, prs);
+      pair<false, P1>(l + 1, total, ps, prev, prs);
     }
     for (; l < nL; l += 2) {
       pair<true, 0>(l, total, ps, prev, prs);
-      if (l + 1 < nL) pair<true, 1>(l + 1, total, ps, prev, prs);
+      if (l + 1 < nL) pair<true, P1>(l + 1, total, ps, prev, prs);
     }
-    if ((nL - 1) & 1) finish_any<1>(ps);
+    if ((nL - 1) & 1) finish_any<P1>(ps);
     else finish_any<0>(ps);
   }
 
@@ -407,7 +458,7 @@ struct Fused {
       for (int b = 0; b < CB; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t row = r0 + wrow + 16 * a + 4 * lg + r;
+          const int64_t row = r0 + wrow + (L96 ? 24 * lg + 4 * a : 16 * a + 4 * lg) + r;
           const int64_t col = c0 + wcol + 16 * b + lc;
           if (row < pb.M && col < pb.N) C[row * pb.ldc + col] = accC[a][b][r];
         }
@@ -432,7 +483,7 @@ __global__ __launch_bounds__(4 * L, (L == 64 ? 2 : 1)) void k_fused(GemmOperands
   const Problem &pb = g.pb;
   constexpr int64_t SLABS = L / F::TN;
   const int64_t nS = pb.nJ * SLABS;
-  constexpr int64_t GROUP = (L == 128) ? 4 : 8;   // tile rows per group: an XCD's
+  constexpr int64_t GROUP = (L == 64) ? 8 : 4;    // tile rows per group: an XCD's
   const int64_t grp = lin / (GROUP * nS);          // concurrent workgroups form a GROUP x 8 block
   const int64_t first_i = grp * GROUP;
   const int64_t gsize = min(GROUP, pb.nI - first_i);
@@ -452,10 +503,10 @@ __global__ __launch_bounds__(4 * L, (L == 64 ? 2 : 1)) void k_fused(GemmOperands
 template <typename IT, typename PT, int L, int FORM>
 static hipError_t launch_fused_t(const GemmOperands &g, const void *A, const void *B, void *C,
                                  hipStream_t st) {
-  const int64_t ntiles = g.pb.nI * g.pb.nJ * (L / 64);
+  const int64_t ntiles = g.pb.nI * g.pb.nJ * (L / Fused<IT, PT, L, FORM, false, false>::TN);
   const int64_t per_xcd = (ntiles + 7) / 8;
   const dim3 grid((unsigned)(per_xcd * 8));
-  const dim3 block(4 * L);
+  const dim3 block(Fused<IT, PT, L, FORM, false, false>::NT);
   const IT *a = (const IT *)A;
   const IT *b = (const IT *)B;
   PT *c = (PT *)C;
@@ -476,6 +527,9 @@ static hipError_t launch_fused_l(const GemmOperands &g, const void *A, const voi
   if (g.pb.L == 64)
     return g.form == TDGEMM_SYM ? launch_fused_t<IT, PT, 64, TDGEMM_SYM>(g, A, B, C, st)
                                 : launch_fused_t<IT, PT, 64, TDGEMM_ASYM>(g, A, B, C, st);
+  if (g.pb.L == 96)
+    return g.form == TDGEMM_SYM ? launch_fused_t<IT, PT, 96, TDGEMM_SYM>(g, A, B, C, st)
+                                : launch_fused_t<IT, PT, 96, TDGEMM_ASYM>(g, A, B, C, st);
   return g.form == TDGEMM_SYM ? launch_fused_t<IT, PT, 128, TDGEMM_SYM>(g, A, B, C, st)
                               : launch_fused_t<IT, PT, 128, TDGEMM_ASYM>(g, A, B, C, st);
 }

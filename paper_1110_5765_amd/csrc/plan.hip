@@ -182,7 +182,7 @@ __global__ __launch_bounds__(kThreads) void k_stats(StatsArgs a) {
 // exactly rounded sum is within the budget -- is found by bisection over t
 // from the entries' ranks. Otherwise the greedy runs step by step.
 constexpr int kMaxT = 8;          // up to 512 subblocks along K
-constexpr int kMaxOpt = 3;        // allowed W levels: at most {4, 2, 1}
+constexpr int kMaxOpt = 3;        // allowed W levels: at most {4, 2, 1} or {3, 2, 1}
 
 struct PlanArgs {
   Problem pb;
@@ -295,16 +295,17 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
   if (a.ctrl == TDGEMM_CTRL_ACCEL && n_ent > 0) {
     // Throughput constraint: the pair with the largest current D (lowest l among
     // equals) drops one level while the inner kernel keeps saving at least
-    // accel * nL * units(W_max) units of MFMA work (units(W) = 4 - 4 / W) and that
+    // accel * nL * units(W_max) units of MFMA work (units(W) = 12 - 12 / W, in
+    // twelfths of a W = 1 product, exact for W in {1, 2, 3, 4}) and that
     // D is positive.
     int own = 0;
 #pragma unroll
     for (int t = 0; t < TT; ++t)
-      if (t < T && lane + (int64_t)kWave * t < pb.nL) own += 4 - 4 / a.w_desc[0];
+      if (t < T && lane + (int64_t)kWave * t < pb.nL) own += 12 - 12 / a.w_desc[0];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) own += __shfl_xor(own, off);
     int saved = own;
-    const double target = (a.accel * (double)pb.nL) * (double)(4 - 4 / a.w_desc[0]);
+    const double target = (a.accel * (double)pb.nL) * (double)(12 - 12 / a.w_desc[0]);
     for (;;) {
       double bd = -INFINITY;
       int64_t bl = INT64_MAX;
@@ -318,7 +319,7 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
 #pragma unroll
         for (int v = 0; v < kMaxOpt; ++v)
           if (level[t] == v) { dv = dopt[v][t]; wc = a.w_desc[v]; wn = a.w_desc[v + 1 < kMaxOpt ? v + 1 : v]; }
-        if (dv > bd || (dv == bd && l < bl)) { bd = dv; bl = l; bdelta = (4 - 4 / wc) - (4 - 4 / wn); }
+        if (dv > bd || (dv == bd && l < bl)) { bd = dv; bl = l; bdelta = (12 - 12 / wc) - (12 - 12 / wn); }
       }
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
@@ -489,11 +490,13 @@ hipError_t launch_stats(const StatsArgs &a, int dtype, int L, hipStream_t st) {
   if (blocks == 0) return hipSuccess;
   const unsigned nb = (unsigned)blocks;
   if (dtype == TDGEMM_F64) {
-    if (L == 64) launch_stats_t<double, 64>(a, nb, st);
-    else         launch_stats_t<double, 128>(a, nb, st);
+    if (L == 64)      launch_stats_t<double, 64>(a, nb, st);
+    else if (L == 96) launch_stats_t<double, 96>(a, nb, st);
+    else              launch_stats_t<double, 128>(a, nb, st);
   } else {
-    if (L == 64) launch_stats_t<float, 64>(a, nb, st);
-    else         launch_stats_t<float, 128>(a, nb, st);
+    if (L == 64)      launch_stats_t<float, 64>(a, nb, st);
+    else if (L == 96) launch_stats_t<float, 96>(a, nb, st);
+    else              launch_stats_t<float, 128>(a, nb, st);
   }
   return hipGetLastError();
 }

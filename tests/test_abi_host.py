@@ -90,11 +90,14 @@ def _desc(binding, **kw):
 
 @pytest.mark.parametrize("kw,status", [
     ({}, 0),
-    ({"L": 96}, -2), ({"L": 0}, -1), ({"form": 3}, -1), ({"prec": 7}, -1),
+    ({"L": 96}, -2), ({"L": 96, "w_allowed": 2 | 4 | 8}, 0), ({"L": 80}, -2), ({"L": 0}, -1),
+    ({"form": 3}, -1), ({"prec": 7}, -1),
     ({"in_dtype": 0, "prec": 1}, -2), ({"M": -1}, -1), ({"lda": 100}, -1), ({"ldc": 10}, -1),
-    ({"trans_a": 2}, -1), ({"w_allowed": 4}, -1), ({"w_allowed": 2 | 8}, -2),
+    ({"trans_a": 2}, -1), ({"w_allowed": 4}, -1), ({"w_allowed": 2 | 8}, -1),
     ({"w_allowed": 2 | 32}, -1), ({"ctrl": 9}, -1), ({"snr_db": math.nan}, -1),
-    ({"ctrl": 1, "fixed_w": 3}, -2), ({"ctrl": 1, "fixed_w": 5}, -1), ({"ctrl": 1, "fixed_rmax": 0.0}, -1),
+    ({"ctrl": 1, "fixed_w": 3}, -1), ({"ctrl": 1, "fixed_w": 3, "L": 96}, 0),
+    ({"ctrl": 1, "fixed_w": 4, "L": 96}, -2), ({"ctrl": 2, "fixed_w": 3, "L": 96}, 0),
+    ({"ctrl": 1, "fixed_w": 5}, -1), ({"ctrl": 1, "fixed_rmax": 0.0}, -1),
     ({"ctrl": 2, "sep_q": 0.5}, -1), ({"u_safe": 0.0}, -1), ({"K": 64 * 513, "lda": 64 * 513}, -2),
 ])
 def test_descriptor_validation(binding, lib, kw, status):
@@ -130,15 +133,18 @@ def test_plan_rejects_missing_workspace_and_calibration(binding, lib):
 
 def test_calibrate_argument_errors(binding, lib):
     lib.tdgemm_calibrate_workspace_size.restype = ctypes.c_size_t
-    assert lib.tdgemm_calibrate_workspace_size(96, 5) == 0
+    assert lib.tdgemm_calibrate_workspace_size(80, 5) == 0
     assert lib.tdgemm_calibrate_workspace_size(64, 5) > 0
+    assert lib.tdgemm_calibrate_workspace_size(96, 5) > 0
     f = lib.tdgemm_calibrate
     z = ctypes.c_void_p(0x1000)
     q = (ctypes.c_double * 1)(0.5)    # q < 1 is rejected
     out = (ctypes.c_double * 1)()
     assert f(64, 2, 1, 0, q, 1, z, z, 5, ctypes.c_double(50.0), out, out, out, z, ctypes.c_size_t(1 << 30), None) == -1
     q[0] = 4.0
-    assert f(64, 3, 1, 0, q, 1, z, z, 5, ctypes.c_double(50.0), out, out, out, z, ctypes.c_size_t(1 << 30), None) == -2
+    assert f(64, 3, 1, 0, q, 1, z, z, 5, ctypes.c_double(50.0), out, out, out, z, ctypes.c_size_t(1 << 30), None) == -1
+    assert f(96, 4, 1, 0, q, 1, z, z, 5, ctypes.c_double(50.0), out, out, out, z, ctypes.c_size_t(1 << 30), None) == -2
+    assert f(80, 2, 1, 0, q, 1, z, z, 5, ctypes.c_double(50.0), out, out, out, z, ctypes.c_size_t(1 << 30), None) == -2
     assert f(64, 2, 1, 0, q, 1, z, z, 5, ctypes.c_double(50.0), out, out, out, z, ctypes.c_size_t(16), None) == -3
 
 

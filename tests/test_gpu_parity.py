@@ -8,7 +8,7 @@ Bar (integer and byte work bit-exact; floating point within the stated bound):
 * C: relative Frobenius error <= 1e-12 (FP64 packing) or 1e-5 (FP32 packing),
   and the fused kernel equal to the staged path bit for bit.
 Shapes span several tiles and ragged tails on every axis; both packing forms,
-both block sizes, all three control modes, transposed operands and the empty
+all three block sizes (L = 96 with W = 3), all three control modes, transposed operands and the empty
 and single-row cases are covered.
 """
 import math
@@ -57,6 +57,18 @@ CASES = [
     ("separable_q127", 256, 256, 192, 128, "sym", "f64", "f64", "separable", 0.0, (1, 2), 2, 0, 0),
     ("single_row", 1, 100, 70, 64, "sym", "f64", "f64", "snr", 40.0, (1, 2), 2, 0, 0),
     ("k_below_L", 70, 20, 90, 64, "asym", "f64", "f64", "snr", 30.0, (1, 2, 4), 2, 0, 0),
+    # L = 96: packings {1, 2, 3}
+    ("L96_sym_snr30_w3", 300, 400, 260, 96, "sym", "f64", "f64", "snr", 30.0, (1, 2, 3), 2, 0, 0),
+    ("L96_asym_snr30_w3", 300, 400, 260, 96, "asym", "f64", "f64", "snr", 30.0, (1, 2, 3), 2, 0, 0),
+    ("L96_sym_fixed_w3", 200, 288, 200, 96, "sym", "f64", "f64", "fixed", 0.0, (1, 3), 3, 0, 0),
+    ("L96_asym_fixed_w3", 200, 288, 200, 96, "asym", "f64", "f64", "fixed", 0.0, (1, 3), 3, 0, 0),
+    ("L96_asym_snr50", 192, 300, 96, 96, "asym", "f64", "f64", "snr", 50.0, (1, 2, 3), 2, 0, 0),
+    ("L96_trans_ab", 150, 200, 90, 96, "asym", "f64", "f64", "snr", 30.0, (1, 2, 3), 2, 1, 1),
+    ("L96_trans_a_sym", 150, 200, 90, 96, "sym", "f64", "f64", "snr", 30.0, (1, 2, 3), 2, 1, 0),
+    ("L96_f32_in", 200, 300, 100, 96, "sym", "f32", "f64", "snr", 40.0, (1, 2, 3), 2, 0, 0),
+    ("L96_f32_pack_sym", 200, 300, 100, 96, "sym", "f32", "f32", "snr", 15.0, (1, 2), 2, 0, 0),
+    ("L96_f32_pack_asym", 200, 300, 100, 96, "asym", "f32", "f32", "snr", 10.0, (1, 2), 2, 0, 0),
+    ("L96_separable_w3", 192, 192, 192, 96, "sym", "f64", "f64", "separable", 0.0, (1, 3), 3, 0, 0),
 ]
 
 
@@ -80,6 +92,8 @@ def test_stagewise_parity(td, case):
     dt = np.float64 if ind == "f64" else np.float32
     A, B, Ad, Bd = _inputs(M, K, N, dt, ta, tb, seed=zlib.crc32(name.encode()))
     rmax = float(2 ** 20) if L == 64 else float(2 ** 21)
+    if fw == 3:
+        rmax = float(2 ** 14)            # three 16-bit slots: inside the FP64 mantissa
     calib, tabs = device_calib(td, L, form, prec, tuple(w for w in wal if w > 1) or (2,))
     cfg = oracle_cfg(L, form, prec, ctrl, snr, wal, fw, rmax, 127.0)
     res = pl.run(A, B, cfg, calib=tabs, keep=True)
@@ -131,7 +145,7 @@ def test_stagewise_parity(td, case):
     ref = A.astype(np.float64) @ B.astype(np.float64)
     log(f"[parity] {name}: C rel err {rel_err(Cs, res.C):.3e} (bit-exact: {exact_c}), "
         f"SNR vs FP64 {pl.snr_db(Cs, ref):.2f} dB, W hist "
-        f"{ {w: int((pairs['w'] == w).sum()) for w in (1, 2, 4)} }")
+        f"{ {w: int((pairs['w'] == w).sum()) for w in (1, 2, 3, 4)} }")
 
 
 def test_fused_deterministic(td):
@@ -158,7 +172,8 @@ def test_empty_shapes(td, M, K, N):
 
 @pytest.mark.parametrize("form,prec,W,L", [("sym", "f64", 2, 64), ("asym", "f64", 2, 64),
                                            ("sym", "f64", 4, 64), ("sym", "f32", 2, 64),
-                                           ("asym", "f64", 2, 128)])
+                                           ("asym", "f64", 2, 128), ("sym", "f64", 3, 96),
+                                           ("asym", "f64", 3, 96), ("asym", "f64", 2, 96)])
 def test_calibration_parity(td, form, prec, W, L):
     """Sec. 4.B measurement on the GPU path equals the oracle's on the same draws."""
     from oracle import calibration as cal

@@ -26,8 +26,12 @@ def td():
     return tdgemm
 
 
+def _wmax(L):
+    return 3 if L == 96 else 4
+
+
 def _calib(kind, L, form):
-    tabs = tables(L, form, "f64", (2, 4))
+    tabs = tables(L, form, "f64", (2, _wmax(L)))
     r = tabs[2].r
     if kind == "scaled_w4":          # W = 4 cheaper than W = 2: D need not fall with W
         tabs = {2: tabs[2], 4: ct.CalibTable(r.copy(), tabs[2].s * 0.25)}
@@ -45,6 +49,8 @@ CASES = [
     ("nonmono_fallback", 192, 640, 128, 64, "sym", 86.0, (1, 2, 4), "gauss", "scaled_w4"),
     ("unavailable_w4", 128, 512, 192, 64, "sym", 80.0, (1, 2, 4), "laplace", "no_w4"),
     ("deep_prune_w2_only", 256, 1024, 64, 64, "sym", 80.0, (1, 2), "laplace", "std"),
+    ("L96_many_l", 96, 96 * 70, 96, 96, "sym", 30.0, (1, 2, 3), "gauss", "std"),
+    ("L96_asym_ragged", 64, 96 * 50 + 17, 70, 96, "asym", 25.0, (1, 2, 3), "laplace", "std"),
 ]
 
 
@@ -68,7 +74,7 @@ def test_plan_parity(td, case):
     tabs = _calib(ckind, L, form)
     cfg = oracle_cfg(L, form, "f64", "snr", snr, wal, 2, 1.0, 127.0)
     ref = pl.make_plan(A, B, cfg, calib=tabs)
-    calib = td.DeviceCalib(tabs[2].r, {W: tabs[W].s for W in (2, 4)})
+    calib = td.DeviceCalib(tabs[2].r, {W: tabs[W].s for W in (2, _wmax(L))})
     Ad, Bd = to_dev(A), to_dev(B)
     desc = td.make_desc(Ad, Bd, L=L, form=form, prec="f64", ctrl="snr", snr_db=snr, w_allowed=wal)
     plan = td.tdgemm_plan(desc, Ad, Bd, calib)
@@ -99,6 +105,8 @@ ACCEL_CASES = [
     ("accel_w24_f06", 256, 1024, 64, 64, "sym", 0.6, (1, 2, 4), "laplace"),
     ("accel_L128_many_l", 128, 128 * 70, 128, 128, "sym", 0.45, (1, 2, 4), "gauss"),
     ("accel_ties", 128, 384, 128, 64, "sym", 0.5, (1, 2), "tiled"),
+    ("accel_L96_w23", 192, 96 * 20, 96, 96, "sym", 0.55, (1, 2, 3), "laplace"),
+    ("accel_L96_asym", 96, 96 * 12, 192, 96, "asym", 0.3, (1, 2, 3), "gauss"),
 ]
 
 
@@ -111,7 +119,7 @@ def test_accel_plan_parity(td, case):
     tabs = _calib("std", L, form)
     cfg = pl.Config(L=L, form=form, prec="f64", ctrl="accel", accel=frac, w_allowed=tuple(wal))
     ref = pl.make_plan(A, B, cfg, calib=tabs)
-    calib = td.DeviceCalib(tabs[2].r, {W: tabs[W].s for W in (2, 4)})
+    calib = td.DeviceCalib(tabs[2].r, {W: tabs[W].s for W in (2, _wmax(L))})
     Ad, Bd = to_dev(A), to_dev(B)
     desc = td.make_desc(Ad, Bd, L=L, form=form, prec="f64", ctrl="accel", accel=frac, w_allowed=wal)
     plan = td.tdgemm_plan(desc, Ad, Bd, calib)

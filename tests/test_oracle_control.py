@@ -204,3 +204,44 @@ def test_prune_accel_extremes_and_invariants():
 def test_prune_accel_keeps_zero_distortion_pairs():
     opts = [{2: _opt(2, 0.0), 1: _opt(1, 0.0)}, {2: _opt(2, 1.0), 1: _opt(1, 0.0)}]
     assert ct.prune_accel(opts, [2, 1], 0.0) == [2, 1]      # nothing to gain from the first
+
+
+def test_saved_units_are_twelfths_of_the_plain_product():
+    """Throughput units: a pair at packing W runs 1/W of the W = 1 MFMA work, so it
+    saves 1 - 1/W of it; in twelfths this is an integer for every W dividing 12."""
+    from fractions import Fraction
+    for W in (1, 2, 3, 4):
+        assert Fraction(ct.saved_units(W), 12) == 1 - Fraction(1, W)
+    with pytest.raises(ValueError):
+        ct.saved_units(5)
+
+
+def test_prune_accel_three_levels_with_w3_bruteforce():
+    """W in {1, 2, 3}: the result meets the constraint, the next greedy drop would
+    break it, and (brute force) no assignment that meets the constraint and packs
+    every pair at least as much has a smaller distortion sum."""
+    rng = np.random.default_rng(23)
+    for trial in range(150):
+        n = int(rng.integers(1, 6))
+        d2 = rng.exponential(1.0, n) + 0.01
+        d3 = d2 + rng.exponential(2.0, n)
+        opts = [{3: _opt(3, float(d3[l])), 2: _opt(2, float(d2[l])), 1: _opt(1, 0.0)} for l in range(n)]
+        assert ct.prune_accel(opts, [3, 2, 1], 1.0) == [3] * n
+        assert ct.prune_accel(opts, [3, 2, 1], 0.0) == [1] * n
+        frac = float(rng.uniform())
+        w = ct.prune_accel(opts, [3, 2, 1], frac)
+        saved = sum(ct.saved_units(x) for x in w)
+        target = ct.accel_target(n, 3, frac)
+        assert saved >= target
+        cur = [opts[l][w[l]].d for l in range(n)]
+        cand = [l for l in range(n) if w[l] != 1]
+        if cand:
+            l = max(cand, key=lambda x: (cur[x], -x))
+            nxt = {3: 2, 2: 1}[w[l]]
+            assert saved - ct.saved_units(w[l]) + ct.saved_units(nxt) < target
+        dsum = sum(cur)
+        for alt in itertools.product([3, 2, 1], repeat=n):
+            if sum(ct.saved_units(x) for x in alt) < target:
+                continue
+            if all(a >= b for a, b in zip(alt, w)) and alt != tuple(w):
+                assert sum(opts[l][alt[l]].d for l in range(n)) >= dsum

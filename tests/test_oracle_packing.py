@@ -50,10 +50,10 @@ def test_packed_words_and_eq8_expansion_exact(W):
         assert lhs == wanted + side
 
 
-@pytest.mark.parametrize("W", [2, 4])
+@pytest.mark.parametrize("W", [2, 3, 4])
 def test_asym_packed_words_exact(W):
     rng = np.random.default_rng(7 + W)
-    L, q, p = 8, 5, 6
+    L, q, p = 12, 5, 6
     qa = _ints(rng, (L, L), q)
     abar = pk.pack_asym_a(qa, W, p, "f64")
     assert abar.shape == (L // W, L)
@@ -80,7 +80,8 @@ def _asym_roundtrip(qa, qb, W, p, prec):
     ("sym", "f64", 2, 128, 181), ("sym", "f32", 2, 64, 1), ("sym", "f32", 2, 16, 5),
     ("sym", "f64", 3, 48, 26), ("asym", "f64", 2, 64, 161), ("asym", "f64", 2, 64, 50),
     ("asym", "f64", 4, 64, 3), ("asym", "f64", 2, 128, 104), ("asym", "f32", 2, 64, 1),
-    ("asym", "f64", 3, 48, 15)])
+    ("asym", "f64", 3, 48, 15), ("sym", "f64", 3, 96, 15), ("sym", "f64", 2, 96, 209),
+    ("asym", "f64", 3, 96, 8), ("asym", "f64", 2, 96, 126)])
 def test_unpack_equals_bruteforce_in_exact_regime(form, prec, W, L, q):
     rng = np.random.default_rng(L * 1000 + q + W)
     qa = _ints(rng, (L, L), q).astype(pk.DTYPES[prec])
@@ -155,10 +156,9 @@ def test_prop1_numbers_by_hand():
     assert abs(math.log(12673 * 2.0 ** -52) / math.log(1 / 12722) + 1 - 3.8141) < 1e-3
 
 
-@pytest.mark.parametrize("W", [2, 4])
-def test_remark2_storage(W):
+@pytest.mark.parametrize("W,L", [(2, 64), (4, 64), (3, 96), (2, 96)])
+def test_remark2_storage(W, L):
     """Remark 2: symmetric packing stores 2 L^2 / W words, asymmetric L^2 (1 + 1/W)."""
-    L = 64
     qa = np.zeros((L, L))
     sym_words = pk.pack_sym_a(qa, W, 10, "f64").size + pk.pack_sym_b(qa, W, 10, "f64").size
     asym_words = pk.pack_asym_a(qa, W, 10, "f64").size + qa.size
