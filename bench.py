@@ -21,7 +21,8 @@ step and both loss curves are reported.
 S = 50, 40 and 20 dB against plain FP64 and FP32.
 
 --workload sweep-table: the whole 4096^3 throughput-distortion sweep, S in
-{60, 52, 44, 36, 28, 20} dB x {sym, asym} x L in {64, 128} x {Gaussian,
+{60, 52, 44, 36, 28, 20} dB x {sym, asym} x L in {64, 96, 128} (W in {1, 2, 3} at
+L = 96, {1, 2, 4} otherwise) x {Gaussian,
 Laplace}, one line with every point (step time, effective GFLOP/s, SNR, W).
 
 --workload fig7: throughput-controlled single-precision GEMM, 4032^3 with the
@@ -305,13 +306,14 @@ def run_sweep_table(args):
         Bd = torch.from_numpy(B).cuda()
         ref = torch.matmul(Ad, Bd)
         C = torch.empty((n, n), dtype=torch.float64, device="cuda")
-        for L in (64, 128):
+        for L in (64, 96, 128):
+            wmax = 3 if L == 96 else 4                   # packings a block size supports
             for form in ("sym", "asym"):
                 if (L, form) not in calibs:
-                    calibs[(L, form)] = calibrate_gpu(td, torch, L, form, "f64", [2, 4])[0]
+                    calibs[(L, form)] = calibrate_gpu(td, torch, L, form, "f64", [2, wmax])[0]
                 calib = calibs[(L, form)]
                 for S in (60.0, 52.0, 44.0, 36.0, 28.0, 20.0):
-                    desc = td.make_desc(Ad, Bd, L=L, form=form, ctrl="snr", snr_db=S, w_allowed=(1, 2, 4))
+                    desc = td.make_desc(Ad, Bd, L=L, form=form, ctrl="snr", snr_db=S, w_allowed=(1, 2, wmax))
                     ws = torch.empty(td.tdgemm_workspace_size(desc), dtype=torch.uint8, device="cuda")
                     holder = {}
 
@@ -325,7 +327,7 @@ def run_sweep_table(args):
 
                     ms, _ = timed_steps(torch, step, 2, max(5, args.steps // 2), 1)
                     _, _, pairs, _ = td.tdgemm_plan_export(holder["plan"])
-                    wh = {int(w): int((pairs["w"] == w).sum()) for w in (1, 2, 4)}
+                    wh = {int(w): int((pairs["w"] == w).sum()) for w in (1, 2, wmax)}
                     snr = snr_of(torch, C, ref)
                     rows.append({"dist": dist, "L": L, "form": form, "snr_target_db": S, "ms": round(ms, 4),
                                  "gflops": round(flops / ms / 1e6, 1), "snr_db": round(snr, 2),
