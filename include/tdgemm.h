@@ -94,6 +94,13 @@ typedef struct {
                                  everywhere, the pair with the largest D (lowest l on ties)
                                  drops to the next allowed W while the constraint still holds
                                  afterwards and that D is positive. */
+  const double *tile_target;  /* SNR / ACCEL, optional (NULL: snr_db or accel for every inner
+                                 kernel): host array of nI x nJ targets, row-major by inner-kernel
+                                 row i, one per inner kernel R_ij (Sec. 6): S_kernel(i, j) in dB
+                                 (SNR; not NaN, +inf = native precision) or F_kernel(i, j) in
+                                 [0, 1] (ACCEL). nI = ceil(M / L), nJ = ceil(N / L). Read during
+                                 tdgemm_plan only, which then synchronises its stream once. Must
+                                 be NULL in the other control modes. */
 } tdgemm_desc;
 
 /* Representation-noise table s(R_max, W) of Sec. 4.B (eq. 18), device memory:

@@ -16,6 +16,8 @@ Control modes:
 * 'accel'      the same options pruned under the throughput constraint F_kernel (Sec. 6).
 * 'fixed'      one (W, R_max) for every pair with the eq. (26) companders.
 * 'separable'  per-block companders c = Q / max|X| with one Q and W.
+'snr' and 'accel' take one target for all inner kernels or one per inner kernel
+(S_kernel(i, j) or F_kernel(i, j), Sec. 6).
 
 The result keeps every intermediate per pair when ``keep`` is set, indexed by
 (i, j, l), plus the brute-force integer product of the companded blocks.
@@ -39,6 +41,9 @@ class Config:
     ctrl: str = "snr"            # 'snr' | 'accel' | 'fixed' | 'separable'
     snr_db: float = 40.0
     accel: float = 1.0           # 'accel': required fraction F_kernel of the maximum saved work
+    # 'snr' / 'accel': optional per-inner-kernel targets, tile_targets[i][j] = S_kernel(i, j)
+    # in dB or F_kernel(i, j) (Sec. 6); None uses snr_db / accel for every inner kernel
+    tile_targets: tuple | None = None
     w_allowed: tuple = (1, 2)
     fixed_w: int = 2
     fixed_rmax: float = float(2 ** 20)
@@ -103,11 +108,13 @@ def make_plan(A: np.ndarray, B: np.ndarray, cfg: Config, calib: dict | None = No
             options[(i, j, l)] = o
         if cfg.ctrl == "snr":
             terms = [ct.signal_term(bk.valid_extent(K, l, L), sa[i][l], sb[l][j]) for l in range(nL)]
-            dk = ct.kernel_budget(terms, cfg.snr_db)
+            s_ij = cfg.snr_db if cfg.tile_targets is None else cfg.tile_targets[i][j]
+            dk = ct.kernel_budget(terms, s_ij)
             budget[(i, j)] = dk
             ws = ct.prune(opts_l, w_desc, dk)
         elif cfg.ctrl == "accel":
-            ws = ct.prune_accel(opts_l, w_desc, cfg.accel)
+            f_ij = cfg.accel if cfg.tile_targets is None else cfg.tile_targets[i][j]
+            ws = ct.prune_accel(opts_l, w_desc, f_ij)
         else:
             ws = [cfg.fixed_w] * nL
         for l in range(nL):

@@ -88,6 +88,14 @@ tdgemm_status validate(const tdgemm_desc *d) {
     default:
       return TDGEMM_E_ARG;
   }
+  if (d->tile_target) {                                          // per-inner-kernel targets
+    if (d->ctrl != TDGEMM_CTRL_SNR && d->ctrl != TDGEMM_CTRL_ACCEL) return TDGEMM_E_ARG;
+    const int64_t nt = ((d->M + d->L - 1) / d->L) * ((d->N + d->L - 1) / d->L);
+    for (int64_t t = 0; t < nt; ++t) {
+      const double v = d->tile_target[t];
+      if (d->ctrl == TDGEMM_CTRL_SNR ? std::isnan(v) : !(v >= 0.0 && v <= 1.0)) return TDGEMM_E_ARG;
+    }
+  }
   const int64_t nL = (d->K + d->L - 1) / d->L;
   if (nL > 512) return TDGEMM_E_UNSUPPORTED;                     // plan kernel keeps 512 per wave
   return TDGEMM_OK;
@@ -174,6 +182,7 @@ tdgemm_status tdgemm_plan(const tdgemm_desc *desc, const void *A, const void *B,
   tdgemm_plan_s *p = new (std::nothrow) tdgemm_plan_s;
   if (!p) return TDGEMM_E_ARG;
   p->desc = *desc;
+  p->desc.tile_target = nullptr;          // read here only; not kept
   p->ly = ly;
   p->ws = static_cast<char *>(ws);
   p->stream = static_cast<hipStream_t>(stream);
@@ -217,7 +226,20 @@ tdgemm_status tdgemm_plan(const tdgemm_desc *desc, const void *A, const void *B,
       pl.sep_q = desc->sep_q;
       pl.u_safe = desc->u_safe;
       pl.snr_lin = std::pow(10.0, -desc->snr_db / 10.0);
-      e = tdg::launch_plan(pl, p->stream);
+      pl.tile = nullptr;
+      if (desc->tile_target) {
+        // per inner kernel: 10^(-S/10) (SNR) or F_kernel (ACCEL), copied next to the plan
+        const int64_t nt = ly.nI * ly.nJ;
+        std::vector<double> h(nt);
+        for (int64_t t = 0; t < nt; ++t)
+          h[t] = desc->ctrl == TDGEMM_CTRL_SNR ? std::pow(10.0, -desc->tile_target[t] / 10.0)
+                                               : desc->tile_target[t];
+        double *dt = reinterpret_cast<double *>(p->ws + ly.off_target);
+        e = hipMemcpyAsync(dt, h.data(), sizeof(double) * nt, hipMemcpyHostToDevice, p->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);   // h is released below
+        pl.tile = dt;
+      }
+      if (e == hipSuccess) e = tdg::launch_plan(pl, p->stream);
     }
     if (e != hipSuccess) {
       delete p;

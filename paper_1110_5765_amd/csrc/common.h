@@ -218,7 +218,7 @@ struct PlanTable {
 // Workspace layout shared by the host code and the kernels.
 struct Layout {
   int64_t nI, nL, nJ, n_pairs;
-  size_t off_stats_a, off_stats_b, off_pairs, off_budget, off_table, total;
+  size_t off_stats_a, off_stats_b, off_pairs, off_budget, off_target, off_table, total;
 };
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -234,6 +234,7 @@ __host__ inline Layout make_layout(int64_t M, int64_t N, int64_t K, int L) {
   ly.off_stats_b = off; off = align256(off + sizeof(tdgemm_block_stats) * ly.nL * ly.nJ);
   ly.off_pairs = off;   off = align256(off + sizeof(tdgemm_pair) * ly.n_pairs);
   ly.off_budget = off;  off = align256(off + sizeof(double) * ly.nI * ly.nJ);
+  ly.off_target = off;  off = align256(off + sizeof(double) * ly.nI * ly.nJ);
   ly.off_table = off;   off = align256(off + sizeof(PlanTable));
   ly.total = off;
   return ly;

@@ -202,6 +202,7 @@ struct PlanArgs {
   double fixed_rmax, sep_q, u_safe;
   double snr_lin;                      // 10^(-S/10), computed on the host
   double accel;                        // F_kernel of the throughput constraint
+  const double *tile;                  // per-inner-kernel snr_lin / accel, or nullptr
 };
 
 __device__ __forceinline__ int srow(int W) { return W - 2; }   // s table row of W
@@ -305,7 +306,8 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) own += __shfl_xor(own, off);
     int saved = own;
-    const double target = (a.accel * (double)pb.nL) * (double)(12 - 12 / a.w_desc[0]);
+    const double frac = a.tile ? a.tile[i * pb.nJ + j] : a.accel;
+    const double target = (frac * (double)pb.nL) * (double)(12 - 12 / a.w_desc[0]);
     for (;;) {
       double bd = -INFINITY;
       int64_t bl = INT64_MAX;
@@ -338,7 +340,7 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
       }
     }
   } else if (a.ctrl == TDGEMM_CTRL_SNR && n_ent > 0) {
-    budget = a.snr_lin * wave_csum(sig);
+    budget = (a.tile ? a.tile[i * pb.nJ + j] : a.snr_lin) * wave_csum(sig);
     // does every pair's D decrease strictly along its entries (and weakly to the floor)?
     bool mono = true;
 #pragma unroll
@@ -442,7 +444,7 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
       }
     }
   } else if (a.ctrl == TDGEMM_CTRL_SNR) {
-    budget = a.snr_lin * wave_csum(sig);
+    budget = (a.tile ? a.tile[i * pb.nJ + j] : a.snr_lin) * wave_csum(sig);
   }
 
   // final records
@@ -522,6 +524,7 @@ hipError_t launch_plan(const PlanLaunch &p, hipStream_t st) {
   a.u_safe = p.u_safe;
   a.snr_lin = p.snr_lin;
   a.accel = p.accel;
+  a.tile = p.tile;
   const int64_t tiles = p.pb.nI * p.pb.nJ;
   const unsigned blocks = (unsigned)((tiles + (kThreads / kWave) - 1) / (kThreads / kWave));
   const int64_t T = (p.pb.nL + kWave - 1) / kWave;

@@ -35,7 +35,8 @@ class Desc(ctypes.Structure):
                 ("form", ctypes.c_int32), ("ctrl", ctypes.c_int32), ("w_allowed", ctypes.c_uint32),
                 ("fixed_w", ctypes.c_int32), ("snr_db", ctypes.c_double),
                 ("fixed_rmax", ctypes.c_double), ("sep_q", ctypes.c_double),
-                ("u_safe", ctypes.c_double), ("accel", ctypes.c_double)]
+                ("u_safe", ctypes.c_double), ("accel", ctypes.c_double),
+                ("tile_target", ctypes.c_void_p)]
 
 
 class Calib(ctypes.Structure):
@@ -148,7 +149,7 @@ def make_desc(A: torch.Tensor, B: torch.Tensor, *, L: int = 64, form: str = "sym
               prec: str | None = None, ctrl: str = "snr", snr_db: float = 40.0,
               w_allowed=(1, 2, 4), fixed_w: int = 2, fixed_rmax: float = float(2 ** 20),
               sep_q: float = 127.0, u_safe: float = 50.0, accel: float = 1.0,
-              ldc: int | None = None) -> Desc:
+              ldc: int | None = None, tile_target=None) -> Desc:
     M, K = A.shape
     K2, N = B.shape
     if K != K2:
@@ -174,6 +175,15 @@ def make_desc(A: torch.Tensor, B: torch.Tensor, *, L: int = 64, form: str = "sym
     d.sep_q = sep_q
     d.u_safe = u_safe
     d.accel = accel
+    if tile_target is not None:
+        # host array nI x nJ of per-inner-kernel targets (S in dB or F_kernel); the
+        # descriptor keeps it alive for tdgemm_plan
+        nI, nJ = -(-M // L), -(-N // L)
+        t = np.ascontiguousarray(np.asarray(tile_target, dtype=np.float64))
+        if t.shape != (nI, nJ):
+            raise ValueError(f"tile_target must be {nI} x {nJ}, got {t.shape}")
+        d._tile_keep = t
+        d.tile_target = t.ctypes.data
     return d
 
 

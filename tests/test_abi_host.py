@@ -114,6 +114,24 @@ def test_descriptor_validation(binding, lib, kw, status):
         assert not h.value
 
 
+@pytest.mark.parametrize("ctrl,values,status", [
+    (0, [30.0, math.inf, -5.0, 80.0], 0), (0, [30.0, math.nan, 20.0, 20.0], -1),
+    (3, [0.0, 1.0, 0.5, 0.25], 0), (3, [0.5, 1.5, 0.5, 0.5], -1), (3, [0.5, -0.1, 0.5, 0.5], -1),
+    (1, [30.0, 30.0, 30.0, 30.0], -1), (2, [30.0, 30.0, 30.0, 30.0], -1)])
+def test_tile_target_validation(binding, lib, ctrl, values, status):
+    """Per-inner-kernel targets (2 x 2 inner kernels): checked on the host."""
+    d = _desc(binding, M=128, N=100, ctrl=ctrl, ldc=100)
+    arr = (ctypes.c_double * 4)(*values)
+    d.tile_target = ctypes.cast(arr, ctypes.c_void_p).value
+    size = lib.tdgemm_workspace_size
+    size.restype = ctypes.c_size_t
+    assert (size(ctypes.byref(d)) > 0) == (status == 0)
+    if status != 0:
+        h = ctypes.c_void_p()
+        assert lib.tdgemm_plan(ctypes.byref(d), None, None, None, None, ctypes.c_size_t(0), None,
+                               ctypes.byref(h)) == status
+
+
 def test_plan_rejects_missing_workspace_and_calibration(binding, lib):
     d = _desc(binding)
     h = ctypes.c_void_p()

@@ -3,6 +3,7 @@ on inputs chosen to stress the pruning: equal noise values across subblocks,
 more than 64 subblocks along K, calibration tables under which D does not
 decrease with W (the step-by-step greedy) and tables with no usable W = 4
 point. Records and budgets must equal the oracle's bit for bit."""
+import math
 import zlib
 
 import numpy as np
@@ -139,3 +140,43 @@ def test_accel_plan_parity(td, case):
         Cref = pl.run(A, B, cfg, calib=tabs, plan=ref).C
         got = C.cpu().numpy()
         assert float(np.linalg.norm(got - Cref) / np.linalg.norm(Cref)) <= 1e-12
+
+
+@pytest.mark.parametrize("ctrl,L,form", [("snr", 64, "sym"), ("snr", 96, "asym"), ("accel", 128, "sym")])
+def test_tile_target_plan_parity(td, ctrl, L, form):
+    """Per-inner-kernel targets S_kernel(i, j) / F_kernel(i, j) (Sec. 6): records and
+    budgets bit-exact to the oracle, and the product of the packed path."""
+    M, K, N = 5 * L - 17, 4 * L, 4 * L + 9
+    nI, nJ = -(-M // L), -(-N // L)
+    rng = np.random.default_rng(41 + L)
+    if ctrl == "snr":
+        tmap = rng.choice([math.inf, 70.0, 45.0, 30.0, 22.0, 15.0], size=(nI, nJ))
+    else:
+        tmap = rng.choice([0.0, 0.2, 0.5, 0.8, 1.0], size=(nI, nJ))
+    log(f"[plan] tile targets {ctrl} L={L} {form}: {nI} x {nJ}")
+    A, B = _inputs("laplace", M, K, N, 77 + L)
+    tabs = _calib("std", L, form)
+    wal = (1, 2, _wmax(L))
+    cfg = pl.Config(L=L, form=form, prec="f64", ctrl=ctrl, snr_db=40.0, w_allowed=wal,
+                    tile_targets=tuple(tuple(float(v) for v in row) for row in tmap))
+    ref = pl.make_plan(A, B, cfg, calib=tabs)
+    calib = td.DeviceCalib(tabs[2].r, {W: tabs[W].s for W in (2, _wmax(L))})
+    Ad, Bd = to_dev(A), to_dev(B)
+    desc = td.make_desc(Ad, Bd, L=L, form=form, prec="f64", ctrl=ctrl, snr_db=40.0, w_allowed=wal,
+                        tile_target=tmap)
+    plan = td.tdgemm_plan(desc, Ad, Bd, calib)
+    sa, sb, pairs, budget = td.tdgemm_plan_export(plan)
+
+    class _Res:
+        pass
+    res = _Res()
+    res.plan = ref
+    compare_plan(pairs, budget, sa, sb, res, [(i, j) for i in range(nI) for j in range(nJ)])
+    if ctrl == "snr":
+        assert np.all(pairs["w"][tmap == math.inf] == 1)
+    C = torch.empty((M, N), dtype=torch.float64, device="cuda")
+    td.tdgemm_gemm(plan, Ad, Bd, C, fused=1)
+    Cref = pl.run(A, B, cfg, calib=tabs, plan=ref).C
+    got = C.cpu().numpy()
+    assert float(np.linalg.norm(got - Cref) / np.linalg.norm(Cref)) <= 1e-12
+    log(f"[plan] tile targets {ctrl}: W histogram {np.bincount(pairs['w'].ravel(), minlength=5).tolist()}")

@@ -16,6 +16,7 @@
 * Fig. 7 / Sec. 7: with every pair at W = 2 in single precision, symmetric
   packing is more accurate than asymmetric packing.
 """
+import dataclasses
 import itertools
 import math
 
@@ -245,3 +246,34 @@ def test_prune_accel_three_levels_with_w3_bruteforce():
                 continue
             if all(a >= b for a, b in zip(alt, w)) and alt != tuple(w):
                 assert sum(opts[l][alt[l]].d for l in range(n)) >= dsum
+
+
+def test_per_tile_targets():
+    """Sec. 6: each inner kernel R_ij is pruned to its own S_kernel(i, j) (or
+    F_kernel(i, j)). A uniform map equals the single target; +inf keeps a tile
+    native; each tile of a mixed map equals the plan made with that tile's
+    target alone."""
+    rng = np.random.default_rng(31)
+    A = rng.standard_normal((128, 256))
+    B = rng.laplace(0.0, 1.0, (256, 192))
+    calib = {W: tables(64, "sym", "f64", (2, 4))[W] for W in (2, 4)}
+    base = pl.Config(L=64, form="sym", ctrl="snr", snr_db=30.0, w_allowed=(1, 2, 4))
+    ref = pl.make_plan(A, B, base, calib)
+    uni = pl.make_plan(A, B, dataclasses.replace(base, tile_targets=((30.0,) * 3,) * 2), calib)
+    assert uni.chosen == ref.chosen and uni.budget == ref.budget
+    smap = ((math.inf, 20.0, 45.0), (60.0, 30.0, 25.0))
+    mixed = pl.make_plan(A, B, dataclasses.replace(base, tile_targets=smap), calib)
+    assert all(mixed.chosen[(0, 0, l)].W == 1 for l in range(4))
+    for i in range(2):
+        for j in range(3):
+            one = pl.make_plan(A, B, dataclasses.replace(base, snr_db=smap[i][j]), calib, tiles=[(i, j)])
+            assert all(mixed.chosen[(i, j, l)] == one.chosen[(i, j, l)] for l in range(4))
+            assert mixed.budget[(i, j)] == one.budget[(i, j)]
+    fmap = ((0.0, 1.0, 0.5), (0.25, 0.75, 1.0))
+    acc = dataclasses.replace(base, ctrl="accel", tile_targets=fmap)
+    got = pl.make_plan(A, B, acc, calib)
+    for i in range(2):
+        for j in range(3):
+            one = pl.make_plan(A, B, dataclasses.replace(base, ctrl="accel", accel=fmap[i][j]), calib,
+                               tiles=[(i, j)])
+            assert all(got.chosen[(i, j, l)] == one.chosen[(i, j, l)] for l in range(4))
