@@ -49,7 +49,8 @@ typedef enum {
 enum { TDGEMM_F64 = 0, TDGEMM_F32 = 1,                        /* element types */
        TDGEMM_I8 = 2, TDGEMM_E4M3 = 3 };                       /* block-scaled forms (prec only) */
 enum { TDGEMM_SYM = 1, TDGEMM_ASYM = 2 };                      /* packing forms */
-enum { TDGEMM_CTRL_SNR = 0, TDGEMM_CTRL_FIXED = 1, TDGEMM_CTRL_SEPARABLE = 2, TDGEMM_CTRL_ACCEL = 3 };
+enum { TDGEMM_CTRL_SNR = 0, TDGEMM_CTRL_FIXED = 1, TDGEMM_CTRL_SEPARABLE = 2, TDGEMM_CTRL_ACCEL = 3,
+       TDGEMM_CTRL_TARGET = 4 };
 
 typedef struct {
   int64_t M, N, K;
@@ -77,14 +78,24 @@ typedef struct {
                                  SEPARABLE: every pair at packing fixed_w with per-block
                                         companders c = sep_q / max|block| (Sec. 3.A);
                                  ACCEL: the SNR-mode options pruned under the throughput
-                                        constraint F_kernel = accel (Sec. 6). */
+                                        constraint F_kernel = accel (Sec. 6);
+                                 TARGET: every pair at packing fixed_w and range fixed_rmax
+                                        with the Prop. 3 companders (eq. 22, the root with
+                                        c_A >= c_A*) reaching the expected subblock SNR
+                                        snr_db, s(R_max, W) read from the calibration table
+                                        at the smallest grid R >= fixed_rmax; where eq. (25)
+                                        fails (snr_db beyond what fixed_rmax allows) the
+                                        eq. (26) companders, the highest SNR at fixed_rmax. */
   uint32_t w_allowed;         /* SNR / ACCEL: bit w set => packing W = w allowed; bit 1
                                  (W = 1, native arithmetic) must be set; W in {1, 2, 4}, or
                                  {1, 2, 3} at L = 96 */
-  int32_t fixed_w;            /* FIXED / SEPARABLE: W in {1, 2, 4}, or {1, 2, 3} at L = 96 */
+  int32_t fixed_w;            /* FIXED / SEPARABLE / TARGET: W in {1, 2, 4}, or {1, 2, 3} at
+                                 L = 96 */
   double snr_db;              /* SNR mode: S_kernel(i, j) in dB for every inner kernel
-                                 (Sec. 6); +inf requests native precision everywhere */
-  double fixed_rmax;          /* FIXED: R_max of eqs. (17), (24) */
+                                 (Sec. 6); +inf requests native precision everywhere.
+                                 TARGET: the expected subblock SNR in dB (not -inf; +inf
+                                 asks for the highest fixed_rmax allows) */
+  double fixed_rmax;          /* FIXED / TARGET: R_max of eqs. (17), (24) */
   double sep_q;               /* SEPARABLE: integer range Q >= 1 of the rounded operands */
   double u_safe;              /* eq. (15) safety term, normally 50 */
   double accel;               /* ACCEL: F_kernel in [0, 1]. Each inner kernel keeps saving at
@@ -97,8 +108,9 @@ typedef struct {
   const double *tile_target;  /* SNR / ACCEL, optional (NULL: snr_db or accel for every inner
                                  kernel): host array of nI x nJ targets, row-major by inner-kernel
                                  row i, one per inner kernel R_ij (Sec. 6): S_kernel(i, j) in dB
-                                 (SNR; not NaN, +inf = native precision) or F_kernel(i, j) in
-                                 [0, 1] (ACCEL). nI = ceil(M / L), nJ = ceil(N / L). Read during
+                                 (SNR; not NaN, +inf = native precision), F_kernel(i, j) in
+                                 [0, 1] (ACCEL), or the expected subblock SNR in dB of the
+                                 pairs of R_ij (TARGET; not NaN or -inf). nI = ceil(M / L), nJ = ceil(N / L). Read during
                                  tdgemm_plan only, which then synchronises its stream once. Must
                                  be NULL in the other control modes. */
 } tdgemm_desc;
@@ -144,6 +156,7 @@ size_t tdgemm_workspace_size(const tdgemm_desc *desc);
  * squares), per-pair options for every allowed W (eq. 26 companders at the R_max
  * minimising the eq. 27 noise over the calibrated grid, z from eq. 15, D_W from
  * eq. 21) and, per inner kernel, top-down pruning to the SNR budget.
+ * calib is also required in TARGET mode (s(R_max, W) of eq. 23).
  * A, B: device inputs (described by desc). calib: required in SNR mode, else
  * may be NULL. ws: device workspace of ws_bytes >= tdgemm_workspace_size(desc);
  * it holds the plan and must outlive it. On success *out receives a new plan

@@ -28,13 +28,14 @@ Readings taken:
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass
 
 import numpy as np
 
 from .blocks import BlockStats
 from .exactsum import exact_sum
-from .noise import c_tot_eq24, combined_noise_eq21, companders_eq26, nsr_prop4
+from .noise import c_tot_eq24, combined_noise_eq21, companders_eq22, companders_eq26, nsr_prop4
 from .packing import packing_exponent
 
 D_UNAVAILABLE = 1e300
@@ -122,6 +123,37 @@ def fixed_option(W: int, L_eff: int, sa: BlockStats, sb: BlockStats, r_max: floa
     if sa.amax == 0.0 or sb.amax == 0.0:
         return option_zero(W, u_safe)
     return option_at(W, L_eff, sa, sb, r_max, 0.0, u_safe)
+
+
+def table_s_at(table: CalibTable, r_max: float, W: int) -> float:
+    """s(R_max, W) read from a calibrated grid: the value at the smallest grid R
+    not below R_max (s grows with R, so this errs on the safe side); +inf beyond
+    the grid or at an unusable point."""
+    k = int(np.searchsorted(table.r, r_max, side="left"))
+    return float(table.s[k]) if k < table.r.size else math.inf
+
+
+def target_option(W: int, L_eff: int, sa: BlockStats, sb: BlockStats, r_max: float,
+                  s_rep: float, snr_db: float, u_safe: float) -> PairOption:
+    """Prop. 3: a fixed (W, R_max) with the eq. (22) companders that reach the
+    expected subblock SNR snr_db (the root with c_A >= c_A*, eq. 22 with +).
+    When eq. (25) does not hold -- the target is beyond what R_max allows --
+    the double root is taken, which is the eq. (26) pair: the highest expected
+    SNR at this R_max."""
+    if W == 1:
+        return option_native()
+    if sa.amax == 0.0 or sb.amax == 0.0:
+        return option_zero(W, u_safe)
+    s_a, s_b = sa.sigma, sb.sigma
+    ctot = c_tot_eq24(float(L_eff), sa.amax, sb.amax, r_max)
+    cc = companders_eq22(float(L_eff), s_a, s_b, snr_db, ctot, s_rep, +1)
+    c_a, c_b = cc if cc is not None else companders_eq26(s_a, s_b, ctot)
+    q_a = float(np.rint(c_a * sa.amax))
+    q_b = float(np.rint(c_b * sb.amax))
+    r_safe = (float(L_eff) * q_a) * q_b
+    p = packing_exponent(r_safe, u_safe)
+    d = combined_noise_eq21(float(L_eff), s_a, s_b, c_a, c_b, s_rep)
+    return PairOption(W, r_max, c_a, c_b, q_a, q_b, r_safe, p, 1.0 / (c_a * c_b), d, np.nan, s_rep)
 
 
 def separable_option(W: int, L_eff: int, sa: BlockStats, sb: BlockStats, q: float,

@@ -16,8 +16,10 @@ Control modes:
 * 'accel'      the same options pruned under the throughput constraint F_kernel (Sec. 6).
 * 'fixed'      one (W, R_max) for every pair with the eq. (26) companders.
 * 'separable'  per-block companders c = Q / max|X| with one Q and W.
-'snr' and 'accel' take one target for all inner kernels or one per inner kernel
-(S_kernel(i, j) or F_kernel(i, j), Sec. 6).
+* 'target'     one (W, R_max) for every pair with the Prop. 3 companders (eq. 22)
+               that reach the expected subblock SNR snr_db.
+'snr', 'accel' and 'target' take one target for all inner kernels or one per
+inner kernel (S_kernel(i, j) or F_kernel(i, j), Sec. 6).
 
 The result keeps every intermediate per pair when ``keep`` is set, indexed by
 (i, j, l), plus the brute-force integer product of the companded blocks.
@@ -38,7 +40,7 @@ class Config:
     L: int = 64
     form: str = "sym"            # 'sym' (Sec. 3.B) or 'asym' (Sec. 3.C)
     prec: str = "f64"            # packing arithmetic: 'f64' or 'f32'
-    ctrl: str = "snr"            # 'snr' | 'accel' | 'fixed' | 'separable'
+    ctrl: str = "snr"            # 'snr' | 'accel' | 'fixed' | 'separable' | 'target'
     snr_db: float = 40.0
     accel: float = 1.0           # 'accel': required fraction F_kernel of the maximum saved work
     # 'snr' / 'accel': optional per-inner-kernel targets, tile_targets[i][j] = S_kernel(i, j)
@@ -102,6 +104,10 @@ def make_plan(A: np.ndarray, B: np.ndarray, cfg: Config, calib: dict | None = No
                     o[W] = ct.fixed_option(W, L_eff, a, b, cfg.fixed_rmax, cfg.u_safe)
                 elif cfg.ctrl == "separable":
                     o[W] = ct.separable_option(W, L_eff, a, b, cfg.sep_q, cfg.u_safe)
+                elif cfg.ctrl == "target":
+                    s_ij = cfg.snr_db if cfg.tile_targets is None else cfg.tile_targets[i][j]
+                    s_rep = ct.table_s_at(calib[W], cfg.fixed_rmax, W) if W > 1 else 0.0
+                    o[W] = ct.target_option(W, L_eff, a, b, cfg.fixed_rmax, s_rep, s_ij, cfg.u_safe)
                 else:
                     raise ValueError(cfg.ctrl)
             opts_l.append(o)

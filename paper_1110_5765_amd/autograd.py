@@ -66,7 +66,7 @@ class TDContext:
                             w_allowed=c.w_allowed, fixed_w=c.fixed_w, fixed_rmax=c.fixed_rmax,
                             sep_q=c.sep_q)
         ws = self.workspace(desc, A.device)
-        plan = td.tdgemm_plan(desc, A, B, self.calib if c.ctrl == "snr" else None, ws)
+        plan = td.tdgemm_plan(desc, A, B, self.calib if c.ctrl in ("snr", "accel", "target") else None, ws)
         out = torch.empty((M, N), dtype=td.torch_dtype(desc.prec), device=A.device)
         td.tdgemm_gemm(plan, A, B, out, fused=1)
         self.calls += 1

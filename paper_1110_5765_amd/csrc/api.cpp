@@ -79,6 +79,13 @@ tdgemm_status validate(const tdgemm_desc *d) {
       if (!(d->fixed_rmax > 0.0) || !is_finite(d->fixed_rmax)) return TDGEMM_E_ARG;
       break;
     }
+    case TDGEMM_CTRL_TARGET: {
+      const tdgemm_status sw = check_w(d->fixed_w, d->L);
+      if (sw != TDGEMM_OK) return sw;
+      if (!(d->fixed_rmax > 0.0) || !is_finite(d->fixed_rmax)) return TDGEMM_E_ARG;
+      if (std::isnan(d->snr_db) || d->snr_db == -INFINITY) return TDGEMM_E_ARG;
+      break;
+    }
     case TDGEMM_CTRL_SEPARABLE: {
       const tdgemm_status sw = check_w(d->fixed_w, d->L);
       if (sw != TDGEMM_OK) return sw;
@@ -89,11 +96,15 @@ tdgemm_status validate(const tdgemm_desc *d) {
       return TDGEMM_E_ARG;
   }
   if (d->tile_target) {                                          // per-inner-kernel targets
-    if (d->ctrl != TDGEMM_CTRL_SNR && d->ctrl != TDGEMM_CTRL_ACCEL) return TDGEMM_E_ARG;
+    if (d->ctrl != TDGEMM_CTRL_SNR && d->ctrl != TDGEMM_CTRL_ACCEL && d->ctrl != TDGEMM_CTRL_TARGET)
+      return TDGEMM_E_ARG;
     const int64_t nt = ((d->M + d->L - 1) / d->L) * ((d->N + d->L - 1) / d->L);
     for (int64_t t = 0; t < nt; ++t) {
       const double v = d->tile_target[t];
-      if (d->ctrl == TDGEMM_CTRL_SNR ? std::isnan(v) : !(v >= 0.0 && v <= 1.0)) return TDGEMM_E_ARG;
+      const bool ok = d->ctrl == TDGEMM_CTRL_ACCEL ? (v >= 0.0 && v <= 1.0)
+                    : d->ctrl == TDGEMM_CTRL_SNR   ? !std::isnan(v)
+                                                   : !std::isnan(v) && v != -INFINITY;
+      if (!ok) return TDGEMM_E_ARG;
     }
   }
   const int64_t nL = (d->K + d->L - 1) / d->L;
@@ -175,7 +186,7 @@ tdgemm_status tdgemm_plan(const tdgemm_desc *desc, const void *A, const void *B,
   if (has_work && (!A || !B)) return TDGEMM_E_ARG;
   if (!ws || ws_bytes < ly.total) return TDGEMM_E_WORKSPACE;
   const bool with_options = desc->ctrl == TDGEMM_CTRL_SNR || desc->ctrl == TDGEMM_CTRL_ACCEL;
-  if (with_options) {
+  if (with_options || desc->ctrl == TDGEMM_CTRL_TARGET) {
     if (!calib || calib->n_r < 1 || calib->n_r > 512 || !calib->r || !calib->s)
       return TDGEMM_E_CALIB;
   }
@@ -226,14 +237,16 @@ tdgemm_status tdgemm_plan(const tdgemm_desc *desc, const void *A, const void *B,
       pl.sep_q = desc->sep_q;
       pl.u_safe = desc->u_safe;
       pl.snr_lin = std::pow(10.0, -desc->snr_db / 10.0);
+      pl.tgt_pow = std::pow(10.0, 0.1 * desc->snr_db);
       pl.tile = nullptr;
       if (desc->tile_target) {
         // per inner kernel: 10^(-S/10) (SNR) or F_kernel (ACCEL), copied next to the plan
         const int64_t nt = ly.nI * ly.nJ;
         std::vector<double> h(nt);
         for (int64_t t = 0; t < nt; ++t)
-          h[t] = desc->ctrl == TDGEMM_CTRL_SNR ? std::pow(10.0, -desc->tile_target[t] / 10.0)
-                                               : desc->tile_target[t];
+          h[t] = desc->ctrl == TDGEMM_CTRL_SNR    ? std::pow(10.0, -desc->tile_target[t] / 10.0)
+               : desc->ctrl == TDGEMM_CTRL_TARGET ? std::pow(10.0, 0.1 * desc->tile_target[t])
+                                                  : desc->tile_target[t];
         double *dt = reinterpret_cast<double *>(p->ws + ly.off_target);
         e = hipMemcpyAsync(dt, h.data(), sizeof(double) * nt, hipMemcpyHostToDevice, p->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(p->stream);   // h is released below

@@ -149,6 +149,40 @@ __device__ __forceinline__ tdgemm_pair option_at(int W, double L_eff, const Bloc
   return o;
 }
 
+// Prop. 3 at packing W and range r_max: the eq. (22) companders (+ root) reaching
+// the expected subblock SNR S, given as pw = 10^(S/10) (computed on the host);
+// D_QvR of eq. (23) in the form 12 s_a^2 s_b^2 / 10^(S/10) - c_tot^2 (1 + (12 s)^2 / L) / 12.
+// Where eq. (25) fails the double root is taken: the eq. (26) companders.
+__device__ __forceinline__ tdgemm_pair option_target(int W, double L_eff, const BlockMoments &a,
+                                                     const BlockMoments &b, double r_max,
+                                                     double s_rep, double pw, double u_safe) {
+  const double sqrt2 = 1.4142135623730951;    // correctly rounded sqrt(2)
+  double ctot = ((L_eff * a.amax) * b.amax) / r_max;
+  double ss = a.sigma * b.sigma;
+  double rs = 12.0 * s_rep;
+  double d = ((12.0 * ss) * ss) / pw - ((ctot * ctot) * (1.0 + (rs * rs) / L_eff)) / 12.0;
+  double disc = d * d - (((((4.0 * a.sigma) * a.sigma) * b.sigma) * b.sigma) * ctot) * ctot;
+  tdgemm_pair o;
+  if (d < ((2.0 * a.sigma) * b.sigma) * ctot || disc < 0.0) {       // eq. (25) fails
+    o.c_a = sqrt(b.sigma / (a.sigma * ctot));
+    o.c_b = sqrt(a.sigma / (b.sigma * ctot));
+  } else {
+    double root = sqrt(d + sqrt(disc));
+    o.c_a = root / ((sqrt2 * a.sigma) * ctot);
+    o.c_b = (sqrt2 * a.sigma) / root;
+  }
+  o.q_a = rint(o.c_a * a.amax);
+  o.q_b = rint(o.c_b * b.amax);
+  double r_safe = (L_eff * o.q_a) * o.q_b;
+  o.p = packing_exponent(r_safe, u_safe);
+  o.d = noise_eq21(L_eff, a.sigma, b.sigma, o.c_a, o.c_b, s_rep);
+  o.inv = 1.0 / (o.c_a * o.c_b);
+  o.r_max = r_max;
+  o.s_rep = s_rep;
+  o.w = W;
+  return o;
+}
+
 // Per-block companders c = Q / max|X| (same integers for every pair of a block).
 __device__ __forceinline__ tdgemm_pair option_separable(int W, double L_eff, const BlockMoments &a,
                                                         const BlockMoments &b, double q,

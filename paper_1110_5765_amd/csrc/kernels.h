@@ -38,8 +38,10 @@ struct PlanLaunch {
   int block_scaled;                    // INT8 / FP8 form: separable records with W = 1
   double fixed_rmax, sep_q, u_safe, snr_lin;
   double accel;                        // throughput constraint F_kernel (ACCEL control)
-  const double *tile;                  // [nI][nJ] per inner kernel: 10^(-S/10) (SNR) or
-                                       // F_kernel (ACCEL); nullptr: snr_lin / accel everywhere
+  const double *tile;                  // [nI][nJ] per inner kernel: 10^(-S/10) (SNR),
+                                       // F_kernel (ACCEL) or 10^(S/10) (TARGET); nullptr:
+                                       // snr_lin / accel / tgt_pow everywhere
+  double tgt_pow;                      // TARGET: 10^(S/10) of the expected subblock SNR
 };
 
 // Operands of the packed path (all device pointers).

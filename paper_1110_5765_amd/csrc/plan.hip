@@ -202,7 +202,8 @@ struct PlanArgs {
   double fixed_rmax, sep_q, u_safe;
   double snr_lin;                      // 10^(-S/10), computed on the host
   double accel;                        // F_kernel of the throughput constraint
-  const double *tile;                  // per-inner-kernel snr_lin / accel, or nullptr
+  const double *tile;                  // per-inner-kernel snr_lin / accel / tgt_pow, or nullptr
+  double tgt_pow;                      // TARGET: 10^(S/10), computed on the host
 };
 
 __device__ __forceinline__ int srow(int W) { return W - 2; }   // s table row of W
@@ -447,6 +448,18 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
     budget = (a.tile ? a.tile[i * pb.nJ + j] : a.snr_lin) * wave_csum(sig);
   }
 
+  // Prop. 3 control: s(R_max, W) at the smallest grid R not below R_max (+inf
+  // beyond the grid), by bisection over the ascending R values
+  double s_target = 0.0;
+  if (a.ctrl == TDGEMM_CTRL_TARGET && a.fixed_w > 1) {
+    int lo = 0, hi = a.n_r;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (a.calib_r[mid] < a.fixed_rmax) lo = mid + 1; else hi = mid;
+    }
+    s_target = lo < a.n_r ? a.calib_s[srow(a.fixed_w) * a.n_r + lo] : INFINITY;
+  }
+
   // final records
 #pragma unroll
   for (int t = 0; t < TT; ++t) {
@@ -474,6 +487,9 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
       if (W == 1) o = option_native();
       else if (zero) o = option_zero(W, a.u_safe);
       else if (a.ctrl == TDGEMM_CTRL_FIXED) o = option_at(W, L_eff, ma, mb, a.fixed_rmax, 0.0, a.u_safe);
+      else if (a.ctrl == TDGEMM_CTRL_TARGET)
+        o = option_target(W, L_eff, ma, mb, a.fixed_rmax, s_target,
+                          a.tile ? a.tile[i * pb.nJ + j] : a.tgt_pow, a.u_safe);
       else o = option_separable(W, L_eff, ma, mb, a.sep_q, a.u_safe);
     }
     a.pairs[(i * pb.nJ + j) * pb.nL + l] = o;
@@ -525,6 +541,7 @@ hipError_t launch_plan(const PlanLaunch &p, hipStream_t st) {
   a.snr_lin = p.snr_lin;
   a.accel = p.accel;
   a.tile = p.tile;
+  a.tgt_pow = p.tgt_pow;
   const int64_t tiles = p.pb.nI * p.pb.nJ;
   const unsigned blocks = (unsigned)((tiles + (kThreads / kWave) - 1) / (kThreads / kWave));
   const int64_t T = (p.pb.nL + kWave - 1) / kWave;

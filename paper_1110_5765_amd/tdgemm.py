@@ -19,12 +19,13 @@ LIB_PATH = pathlib.Path(__file__).resolve().parent / "libtdgemm.so"
 
 F64, F32, I8, E4M3 = 0, 1, 2, 3
 SYM, ASYM = 1, 2
-CTRL_SNR, CTRL_FIXED, CTRL_SEPARABLE, CTRL_ACCEL = 0, 1, 2, 3
+CTRL_SNR, CTRL_FIXED, CTRL_SEPARABLE, CTRL_ACCEL, CTRL_TARGET = 0, 1, 2, 3, 4
 STATUS = {0: "TDGEMM_OK", -1: "TDGEMM_E_ARG", -2: "TDGEMM_E_UNSUPPORTED",
           -3: "TDGEMM_E_WORKSPACE", -4: "TDGEMM_E_CALIB", -5: "TDGEMM_E_HIP"}
 FORMS = {"sym": SYM, "asym": ASYM}
 PRECS = {"f64": F64, "f32": F32, "i8": I8, "e4m3": E4M3}
-CTRLS = {"snr": CTRL_SNR, "fixed": CTRL_FIXED, "separable": CTRL_SEPARABLE, "accel": CTRL_ACCEL}
+CTRLS = {"snr": CTRL_SNR, "fixed": CTRL_FIXED, "separable": CTRL_SEPARABLE, "accel": CTRL_ACCEL,
+         "target": CTRL_TARGET}
 
 
 class Desc(ctypes.Structure):
@@ -345,7 +346,7 @@ def matmul(A: torch.Tensor, B: torch.Tensor, calib: DeviceCalib | None = None, *
            out: torch.Tensor | None = None, stream=None, **kw) -> tuple[torch.Tensor, Plan]:
     """C = A B through tdgemm_plan + the fused tdgemm_gemm. Keyword arguments as make_desc."""
     desc = make_desc(A, B, **kw)
-    plan = tdgemm_plan(desc, A, B, calib if desc.ctrl in (CTRL_SNR, CTRL_ACCEL) else None,
+    plan = tdgemm_plan(desc, A, B, calib if desc.ctrl in (CTRL_SNR, CTRL_ACCEL, CTRL_TARGET) else None,
                        stream=stream)
     if out is None:
         out = torch.empty((desc.M, desc.N), dtype=torch_dtype(desc.prec), device=A.device)

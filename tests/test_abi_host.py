@@ -99,6 +99,8 @@ def _desc(binding, **kw):
     ({"ctrl": 1, "fixed_w": 4, "L": 96}, -2), ({"ctrl": 2, "fixed_w": 3, "L": 96}, 0),
     ({"ctrl": 1, "fixed_w": 5}, -1), ({"ctrl": 1, "fixed_rmax": 0.0}, -1),
     ({"ctrl": 2, "sep_q": 0.5}, -1), ({"u_safe": 0.0}, -1), ({"K": 64 * 513, "lda": 64 * 513}, -2),
+    ({"ctrl": 4}, 0), ({"ctrl": 4, "snr_db": -math.inf}, -1), ({"ctrl": 4, "fixed_rmax": -1.0}, -1),
+    ({"ctrl": 4, "fixed_w": 3}, -1), ({"ctrl": 4, "snr_db": math.inf}, 0),
 ])
 def test_descriptor_validation(binding, lib, kw, status):
     d = _desc(binding, **kw)
@@ -117,7 +119,8 @@ def test_descriptor_validation(binding, lib, kw, status):
 @pytest.mark.parametrize("ctrl,values,status", [
     (0, [30.0, math.inf, -5.0, 80.0], 0), (0, [30.0, math.nan, 20.0, 20.0], -1),
     (3, [0.0, 1.0, 0.5, 0.25], 0), (3, [0.5, 1.5, 0.5, 0.5], -1), (3, [0.5, -0.1, 0.5, 0.5], -1),
-    (1, [30.0, 30.0, 30.0, 30.0], -1), (2, [30.0, 30.0, 30.0, 30.0], -1)])
+    (1, [30.0, 30.0, 30.0, 30.0], -1), (2, [30.0, 30.0, 30.0, 30.0], -1),
+    (4, [30.0, math.inf, 10.0, 80.0], 0), (4, [30.0, -math.inf, 10.0, 80.0], -1)])
 def test_tile_target_validation(binding, lib, ctrl, values, status):
     """Per-inner-kernel targets (2 x 2 inner kernels): checked on the host."""
     d = _desc(binding, M=128, N=100, ctrl=ctrl, ldc=100)

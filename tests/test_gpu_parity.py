@@ -57,6 +57,10 @@ CASES = [
     ("separable_q127", 256, 256, 192, 128, "sym", "f64", "f64", "separable", 0.0, (1, 2), 2, 0, 0),
     ("single_row", 1, 100, 70, 64, "sym", "f64", "f64", "snr", 40.0, (1, 2), 2, 0, 0),
     ("k_below_L", 70, 20, 90, 64, "asym", "f64", "f64", "snr", 30.0, (1, 2, 4), 2, 0, 0),
+    # Prop. 3 control: a target subblock SNR per pair (the second is out of reach)
+    ("target_sym_s30", 200, 330, 150, 64, "sym", "f64", "f64", "target", 30.0, (1, 2), 2, 0, 0),
+    ("target_asym_s60_capped", 200, 330, 150, 64, "asym", "f64", "f64", "target", 60.0, (1, 2), 2, 0, 0),
+    ("target_L96_w3", 192, 288, 200, 96, "sym", "f64", "f64", "target", 12.0, (1, 3), 3, 0, 0),
     # L = 96: packings {1, 2, 3}
     ("L96_sym_snr30_w3", 300, 400, 260, 96, "sym", "f64", "f64", "snr", 30.0, (1, 2, 3), 2, 0, 0),
     ("L96_asym_snr30_w3", 300, 400, 260, 96, "asym", "f64", "f64", "snr", 30.0, (1, 2, 3), 2, 0, 0),
@@ -100,7 +104,7 @@ def test_stagewise_parity(td, case):
 
     desc = td.make_desc(Ad, Bd, L=L, form=form, prec=prec, ctrl=ctrl, snr_db=snr, w_allowed=wal,
                         fixed_w=fw, fixed_rmax=rmax, sep_q=127.0)
-    plan = td.tdgemm_plan(desc, Ad, Bd, calib if ctrl == "snr" else None)
+    plan = td.tdgemm_plan(desc, Ad, Bd, calib if ctrl in ("snr", "target") else None)
     sa, sb, pairs, budget = td.tdgemm_plan_export(plan)
     nI, nL, nJ, npairs = plan.dims
     tiles = [(i, j) for i in range(nI) for j in range(nJ)]

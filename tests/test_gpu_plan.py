@@ -142,28 +142,33 @@ def test_accel_plan_parity(td, case):
         assert float(np.linalg.norm(got - Cref) / np.linalg.norm(Cref)) <= 1e-12
 
 
-@pytest.mark.parametrize("ctrl,L,form", [("snr", 64, "sym"), ("snr", 96, "asym"), ("accel", 128, "sym")])
+@pytest.mark.parametrize("ctrl,L,form", [("snr", 64, "sym"), ("snr", 96, "asym"), ("accel", 128, "sym"),
+                                         ("target", 64, "asym")])
 def test_tile_target_plan_parity(td, ctrl, L, form):
-    """Per-inner-kernel targets S_kernel(i, j) / F_kernel(i, j) (Sec. 6): records and
+    """Per-inner-kernel targets S_kernel(i, j) / F_kernel(i, j) (Sec. 6), and per-tile
+    subblock targets of the Prop. 3 control: records and
     budgets bit-exact to the oracle, and the product of the packed path."""
     M, K, N = 5 * L - 17, 4 * L, 4 * L + 9
     nI, nJ = -(-M // L), -(-N // L)
     rng = np.random.default_rng(41 + L)
     if ctrl == "snr":
         tmap = rng.choice([math.inf, 70.0, 45.0, 30.0, 22.0, 15.0], size=(nI, nJ))
+    elif ctrl == "target":
+        tmap = rng.choice([math.inf, 50.0, 35.0, 25.0, 15.0], size=(nI, nJ))
     else:
         tmap = rng.choice([0.0, 0.2, 0.5, 0.8, 1.0], size=(nI, nJ))
     log(f"[plan] tile targets {ctrl} L={L} {form}: {nI} x {nJ}")
     A, B = _inputs("laplace", M, K, N, 77 + L)
     tabs = _calib("std", L, form)
     wal = (1, 2, _wmax(L))
-    cfg = pl.Config(L=L, form=form, prec="f64", ctrl=ctrl, snr_db=40.0, w_allowed=wal,
+    cfg = pl.Config(L=L, form=form, prec="f64", ctrl=ctrl, snr_db=40.0, w_allowed=wal, fixed_w=2,
+                    fixed_rmax=float(2 ** 20),
                     tile_targets=tuple(tuple(float(v) for v in row) for row in tmap))
     ref = pl.make_plan(A, B, cfg, calib=tabs)
     calib = td.DeviceCalib(tabs[2].r, {W: tabs[W].s for W in (2, _wmax(L))})
     Ad, Bd = to_dev(A), to_dev(B)
     desc = td.make_desc(Ad, Bd, L=L, form=form, prec="f64", ctrl=ctrl, snr_db=40.0, w_allowed=wal,
-                        tile_target=tmap)
+                        fixed_w=2, fixed_rmax=float(2 ** 20), tile_target=tmap)
     plan = td.tdgemm_plan(desc, Ad, Bd, calib)
     sa, sb, pairs, budget = td.tdgemm_plan_export(plan)
 

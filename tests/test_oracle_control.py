@@ -277,3 +277,60 @@ def test_per_tile_targets():
             one = pl.make_plan(A, B, dataclasses.replace(base, ctrl="accel", accel=fmap[i][j]), calib,
                                tiles=[(i, j)])
             assert all(got.chosen[(i, j, l)] == one.chosen[(i, j, l)] for l in range(4))
+
+
+# --- Prop. 3 fixed-target companders
+
+def test_target_option_reaches_the_target():
+    """Prop. 3: the eq. (22) companders give D = L s_a^2 s_b^2 10^(-S/10) (the target
+    as an MSE), keep c_A c_B = 1 / c_tot (eqs. 17, 24) and, with the + root, c_A >= c_A*.
+    Past eq. (25) the pair falls back to the eq. (26) companders, whose D is the
+    smallest this R_max allows and lies above the target."""
+    rng = np.random.default_rng(51)
+    L = 64
+    A = rng.standard_normal((L, L))
+    B = rng.laplace(0.0, 1.0, (L, L))
+    from oracle import blocks as bk
+    from oracle.noise import c_tot_eq24, companders_eq26, combined_noise_eq21
+    sa, sb = bk.block_stats(A, 0, 0, L), bk.block_stats(B, 0, 0, L)
+    r_max = float(2 ** 16)
+    ctot = c_tot_eq24(float(L), sa.amax, sb.amax, r_max)
+    ca_star, cb_star = companders_eq26(sa.sigma, sb.sigma, ctot)
+    d_min = combined_noise_eq21(float(L), sa.sigma, sb.sigma, ca_star, cb_star, 0.0)
+    sig = float(L) * (sa.sigma * sb.sigma) ** 2
+    s_max = 10.0 * math.log10(sig / d_min)
+    for S in (s_max - 20.0, s_max - 6.0, s_max - 0.5):
+        o = ct.target_option(2, L, sa, sb, r_max, 0.0, S, 50.0)
+        assert abs(o.d / (sig * 10.0 ** (-S / 10.0)) - 1.0) < 1e-9, S
+        assert abs(o.c_a * o.c_b * ctot - 1.0) < 1e-12
+        assert o.c_a >= ca_star and o.c_b <= cb_star
+    for S in (s_max + 0.5, s_max + 10.0, math.inf):
+        o = ct.target_option(2, L, sa, sb, r_max, 0.0, S, 50.0)
+        assert (o.c_a, o.c_b) == (ca_star, cb_star)
+        assert o.d == d_min and o.d > sig * 10.0 ** (-S / 10.0)
+
+
+def test_table_s_at_reads_the_next_grid_point():
+    tab = ct.CalibTable(np.array([10.0, 20.0, 40.0, 80.0]), np.array([0.0, 0.5, np.inf, 2.0]))
+    assert ct.table_s_at(tab, 5.0, 2) == 0.0
+    assert ct.table_s_at(tab, 20.0, 2) == 0.5
+    assert ct.table_s_at(tab, 21.0, 2) == math.inf
+    assert ct.table_s_at(tab, 41.0, 2) == 2.0
+    assert ct.table_s_at(tab, 81.0, 2) == math.inf
+
+
+def test_target_control_meets_the_subblock_snr():
+    """End to end: every pair set by Prop. 3 to S dB; the measured SNR of C against the
+    FP64 product is S within the model's accuracy (exact-regime integers, W = 2)."""
+    rng = np.random.default_rng(52)
+    A = rng.standard_normal((256, 256))
+    B = rng.standard_normal((256, 256))
+    calib = {2: tables(64, "sym", "f64", (2,))[2]}
+    ref = A @ B
+    got = {}
+    for S in (25.0, 40.0, 70.0):
+        cfg = pl.Config(L=64, form="sym", ctrl="target", snr_db=S, w_allowed=(1, 2), fixed_w=2,
+                        fixed_rmax=float(2 ** 22))
+        got[S] = pl.snr_db(pl.run(A, B, cfg, calib=calib).C, ref)
+    assert abs(got[25.0] - 25.0) < 1.0 and abs(got[40.0] - 40.0) < 1.0, got
+    assert 40.0 < got[70.0] < 50.0, got          # beyond reach: the best R_max = 2^22 allows
