@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-k-split", dest="k_split", action="store_false",
+                    help="pca2d: one workgroup per inner kernel (no grouped l-sum)")
     ap.add_argument("--workload", default="sweep",
                     choices=["sweep", "precision", "mlp", "scatter", "sweep-table", "fig7", "pca2d"])
     ap.add_argument("--mlp-steps", type=int, default=200)
@@ -697,13 +699,16 @@ def run_pca2d(args):
     flops = 2.0 * (size * size * Sd.shape[0] + (Sd.shape[0] + Td.shape[0]) * size * d)
     log(f"[bench] 2D-PCA: {n_tr} training and {n_te} test images of {size} x {size}, d = {d}; "
         f"GEMMs G ({size}x{Sd.shape[0]} by {Sd.shape[0]}x{size}) and projections ({Sd.shape[0]} / "
-        f"{Td.shape[0]} x {size} by {size} x {d}), FP32 packing {args.form} L = {L}")
+        f"{Td.shape[0]} x {size} by {size} x {d}), FP32 packing {args.form} L = {L}, "
+        f"k_split {'auto' if args.k_split else 1}")
 
     def gemm(A, B, snr, ws_cache):
         if snr is None:
             return torch.matmul(A, B)
-        desc = td.make_desc(A, B, L=L, form=args.form, prec="f32", ctrl="snr", snr_db=snr, w_allowed=(1, 2))
-        key = (A.shape, B.shape, A.stride(), B.stride())
+        ks = td.auto_k_split(A.shape[0], B.shape[1], A.shape[1], L) if args.k_split else 1
+        desc = td.make_desc(A, B, L=L, form=args.form, prec="f32", ctrl="snr", snr_db=snr, w_allowed=(1, 2),
+                            k_split=ks)
+        key = (A.shape, B.shape, A.stride(), B.stride(), ks)
         if key not in ws_cache:
             ws_cache[key] = torch.empty(td.tdgemm_workspace_size(desc), dtype=torch.uint8, device="cuda")
         plan = td.tdgemm_plan(desc, A, B, calib, ws_cache[key])

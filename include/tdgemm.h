@@ -113,6 +113,14 @@ typedef struct {
                                  pairs of R_ij (TARGET; not NaN or -inf). nI = ceil(M / L), nJ = ceil(N / L). Read during
                                  tdgemm_plan only, which then synchronises its stream once. Must
                                  be NULL in the other control modes. */
+  int32_t k_split;            /* evaluation order of the l-sum of eq. (2): 0 or 1 = one
+                                 ascending sum per inner kernel; k > 1 = groups of
+                                 s = ceil(nL / k) consecutive subblocks, each summed from zero
+                                 in ascending l by its own workgroup of the fused kernel, then
+                                 the ceil(nL / s) group sums added in ascending order to zero
+                                 (more workgroups when M and N give few inner kernels). The
+                                 workspace then holds ceil(nL / s) partial M x N results of
+                                 prec. Not for the block-scaled forms (TDGEMM_E_UNSUPPORTED). */
 } tdgemm_desc;
 
 /* Representation-noise table s(R_max, W) of Sec. 4.B (eq. 18), device memory:

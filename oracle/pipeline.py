@@ -9,7 +9,9 @@ C = A B with A (M x K) and B (K x N), following the paper's flow:
 3. per pair: compand (eq. 3), pack (eqs. 6-7 or 11), packed product (eq. 8
    or 12), unpack (eqs. 9-10 or 13-14)                 -> ``packing``
 4. reverse companding (eq. 5) and the l-sum of eq. (2), l ascending:
-   C_ij = C_ij + r * inv for each pair (W = 1 pairs add their native product).
+   C_ij = C_ij + r * inv for each pair (W = 1 pairs add their native product);
+   with k_groups > 1 the sum runs per group of consecutive l and the group
+   sums are added in ascending order (eq. 2 fixes the sum, not its order).
 
 Control modes:
 * 'snr'        Sec. 5.B / Sec. 6 distortion control with a calibrated s(R, W).
@@ -46,6 +48,10 @@ class Config:
     # 'snr' / 'accel': optional per-inner-kernel targets, tile_targets[i][j] = S_kernel(i, j)
     # in dB or F_kernel(i, j) (Sec. 6); None uses snr_db / accel for every inner kernel
     tile_targets: tuple | None = None
+    # evaluation order of the l-sum of eq. (2): k_groups groups of ceil(nL / k_groups)
+    # consecutive subblocks, each summed from zero in ascending l, then the group sums
+    # added in ascending order to zero (1: one ascending sum)
+    k_groups: int = 1
     w_allowed: tuple = (1, 2)
     fixed_w: int = 2
     fixed_rmax: float = float(2 ** 20)
@@ -180,6 +186,13 @@ def pair_product(a: np.ndarray, b: np.ndarray, opt: ct.PairOption, cfg: Config,
     return contrib, tr
 
 
+def group_size(nl: int, k_groups: int) -> int:
+    """Subblocks per group of the l-sum: ceil(nL / k_groups) (at least 1)."""
+    if k_groups < 1:
+        raise ValueError("k_groups must be >= 1")
+    return max(1, -(-nl // k_groups))
+
+
 def run(A: np.ndarray, B: np.ndarray, cfg: Config, calib: dict | None = None,
         tiles=None, keep: bool = False, plan: Plan | None = None) -> Result:
     """Steps 1-4 over the requested inner kernels (all by default)."""
@@ -193,18 +206,22 @@ def run(A: np.ndarray, B: np.ndarray, cfg: Config, calib: dict | None = None,
     dt = pk.DTYPES[cfg.prec]
     C = np.zeros((M, N), dtype=dt)
     res = Result(plan, C)
+    size = group_size(nL, cfg.k_groups)
     for (i, j) in tiles:
-        acc = np.zeros((L, L), dtype=dt)
-        for l in range(nL):
-            a = bk.block(A, i, l, L)
-            b = bk.block(B, l, j, L)
-            contrib, tr = pair_product(a, b, plan.chosen[(i, j, l)], cfg, keep)
-            acc = (acc + contrib).astype(dt)
-            if keep:
-                res.traces[(i, j, l)] = tr
+        total = np.zeros((L, L), dtype=dt)
+        for l0 in range(0, nL, size):
+            acc = np.zeros((L, L), dtype=dt)
+            for l in range(l0, min(l0 + size, nL)):
+                a = bk.block(A, i, l, L)
+                b = bk.block(B, l, j, L)
+                contrib, tr = pair_product(a, b, plan.chosen[(i, j, l)], cfg, keep)
+                acc = (acc + contrib).astype(dt)
+                if keep:
+                    res.traces[(i, j, l)] = tr
+            total = (total + acc).astype(dt)
         rows = min(L, M - i * L)
         cols = min(L, N - j * L)
-        C[i * L:i * L + rows, j * L:j * L + cols] = acc[:rows, :cols]
+        C[i * L:i * L + rows, j * L:j * L + cols] = total[:rows, :cols]
     return res
 
 

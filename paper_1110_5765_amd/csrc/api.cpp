@@ -44,7 +44,9 @@ tdgemm_status validate(const tdgemm_desc *d) {
   if (d->in_dtype != TDGEMM_F64 && d->in_dtype != TDGEMM_F32) return TDGEMM_E_ARG;
   if (d->prec != TDGEMM_F64 && d->prec != TDGEMM_F32 && !block_scaled(d->prec)) return TDGEMM_E_ARG;
   if (d->prec == TDGEMM_F32 && d->in_dtype == TDGEMM_F64) return TDGEMM_E_UNSUPPORTED;
+  if (d->k_split < 0) return TDGEMM_E_ARG;
   if (block_scaled(d->prec)) {                                   // INT8 / FP8 form
+    if (d->k_split > 1) return TDGEMM_E_UNSUPPORTED;
     if (d->ctrl != TDGEMM_CTRL_SEPARABLE || d->fixed_w != 1) return TDGEMM_E_ARG;
     if (!(d->sep_q >= 1.0) || !(d->sep_q <= (d->prec == TDGEMM_I8 ? 127.0 : 448.0)))
       return TDGEMM_E_ARG;
@@ -112,6 +114,11 @@ tdgemm_status validate(const tdgemm_desc *d) {
   return TDGEMM_OK;
 }
 
+Layout layout_of(const tdgemm_desc &d) {
+  const size_t elem = d.prec == TDGEMM_F32 ? sizeof(float) : sizeof(double);
+  return tdg::make_layout(d.M, d.N, d.K, d.L, d.k_split, elem);
+}
+
 Problem problem_of(const tdgemm_desc &d, const Layout &ly) {
   Problem p;
   p.M = d.M; p.N = d.N; p.K = d.K;
@@ -130,6 +137,7 @@ tdg::GemmOperands operands_of(const tdgemm_plan_s *p) {
   g.ta = p->desc.trans_a != 0;
   g.tb = p->desc.trans_b != 0;
   g.pairs = reinterpret_cast<const tdgemm_pair *>(p->ws + p->ly.off_pairs);
+  g.gsize = p->ly.gsize;
   return g;
 }
 
@@ -171,7 +179,7 @@ const char *tdgemm_status_string(tdgemm_status s) {
 
 size_t tdgemm_workspace_size(const tdgemm_desc *desc) {
   if (validate(desc) != TDGEMM_OK) return 0;
-  return tdg::make_layout(desc->M, desc->N, desc->K, desc->L).total;
+  return layout_of(*desc).total;
 }
 
 tdgemm_status tdgemm_plan(const tdgemm_desc *desc, const void *A, const void *B,
@@ -181,7 +189,7 @@ tdgemm_status tdgemm_plan(const tdgemm_desc *desc, const void *A, const void *B,
   *out = nullptr;
   tdgemm_status s = validate(desc);
   if (s != TDGEMM_OK) return s;
-  const Layout ly = tdg::make_layout(desc->M, desc->N, desc->K, desc->L);
+  const Layout ly = layout_of(*desc);
   const bool has_work = !empty_output(*desc) && desc->K > 0;
   if (has_work && (!A || !B)) return TDGEMM_E_ARG;
   if (!ws || ws_bytes < ly.total) return TDGEMM_E_WORKSPACE;
@@ -353,7 +361,8 @@ tdgemm_status tdgemm_gemm(tdgemm_plan_t plan, const void *a, const void *b, void
     q.out = out;
     return hip_status(tdg::launch_gemm8(q, d.prec, !fused, (hipStream_t)stream));
   }
-  if (fused) return hip_status(tdg::launch_fused(g, a, b, out, (hipStream_t)stream));
+  if (fused)
+    return hip_status(tdg::launch_fused(g, a, b, out, plan->ws + plan->ly.off_part, (hipStream_t)stream));
   return hip_status(tdg::launch_packed_product(g, a, b, out, (hipStream_t)stream));
 }
 
@@ -418,6 +427,7 @@ tdgemm_status tdgemm_calibrate(int32_t L, int32_t W, int32_t form, int32_t prec,
   g.pb.M = g.pb.N = g.pb.K = L;
   g.pb.lda = g.pb.ldb = g.pb.ldc = L;
   g.pb.nI = n_inst; g.pb.nJ = 1; g.pb.nL = 1;
+  g.gsize = 1;
   g.pb.L = L;
   g.in_dtype = prec; g.prec = prec; g.form = form; g.ta = g.tb = false;
   g.pairs = pairs_w;

@@ -252,12 +252,22 @@ struct PlanTable {
 // Workspace layout shared by the host code and the kernels.
 struct Layout {
   int64_t nI, nL, nJ, n_pairs;
-  size_t off_stats_a, off_stats_b, off_pairs, off_budget, off_target, off_table, total;
+  size_t off_stats_a, off_stats_b, off_pairs, off_budget, off_target, off_table, off_part, total;
+  int64_t gsize, ngroups;     // subblocks per group of the l-sum, and the number of groups
 };
+
+// Subblocks per group of the l-sum for k_split groups requested (0 or 1: all).
+__host__ __device__ inline int64_t group_size(int64_t nl, int64_t k_split) {
+  if (k_split <= 1 || nl <= 0) return nl > 0 ? nl : 1;
+  const int64_t s = (nl + k_split - 1) / k_split;
+  return s > 0 ? s : 1;
+}
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-__host__ inline Layout make_layout(int64_t M, int64_t N, int64_t K, int L) {
+// part_elem: bytes per element of the partial results of a split l-sum (0: none).
+__host__ inline Layout make_layout(int64_t M, int64_t N, int64_t K, int L, int64_t k_split = 1,
+                                   size_t part_elem = 0) {
   Layout ly;
   ly.nI = (M + L - 1) / L;
   ly.nL = (K + L - 1) / L;
@@ -270,6 +280,10 @@ __host__ inline Layout make_layout(int64_t M, int64_t N, int64_t K, int L) {
   ly.off_budget = off;  off = align256(off + sizeof(double) * ly.nI * ly.nJ);
   ly.off_target = off;  off = align256(off + sizeof(double) * ly.nI * ly.nJ);
   ly.off_table = off;   off = align256(off + sizeof(PlanTable));
+  ly.gsize = group_size(ly.nL, k_split);
+  ly.ngroups = ly.nL > 0 ? (ly.nL + ly.gsize - 1) / ly.gsize : 1;
+  ly.off_part = off;
+  if (ly.ngroups > 1) off = align256(off + part_elem * (size_t)ly.ngroups * (size_t)M * (size_t)N);
   ly.total = off;
   return ly;
 }

@@ -122,6 +122,7 @@ struct Fused {
   Smem &sm;
   int tid, lg, lc, wr, wrow, wcol;
   int64_t r0, c0;
+  int64_t kb = 0;         // inner index of the first subblock this workgroup sums
   // per-thread load coordinates inside a chunk
   int a_m, a_k;           // first (row, col) this thread loads from A's chunk
   int b_n, b_k;           // (col, first row) of B's chunk
@@ -167,7 +168,8 @@ struct Fused {
   // Raw loads of the chunk starting at inner index k0: a uniform base pointer
   // plus this thread's fixed offset. With CHECK, out-of-range elements read 0.
   template <bool CHECK, int S>
-  __device__ __forceinline__ void load(int64_t k0) {
+  __device__ __forceinline__ void load(int64_t kc0) {
+    const int64_t k0 = kb + kc0;
     const IT *Ab = TA ? A + k0 * pb.lda + r0 : A + r0 * pb.lda + k0;
     const IT *Bb = TB ? B + c0 * pb.ldb + k0 : B + k0 * pb.ldb + c0;
     const int64_t kleft = pb.K - k0, mleft = pb.M - r0;
@@ -427,9 +429,9 @@ struct Fused {
   // for chunks that reach past K (chunk g starts at inner index g KC): pairs
   // whose prefetches all stay inside K run unchecked, the rest checked.
   template <bool CHECK>
-  __device__ __forceinline__ void run(const tdgemm_pair *prs) {
-    const int64_t nL = pb.nL, total = nL * NCH;
-    const int64_t kfull = pb.K / KC;                                  // chunks inside K
+  __device__ __forceinline__ void run(const tdgemm_pair *prs, int64_t nL) {
+    const int64_t total = nL * NCH;
+    const int64_t kfull = (pb.K - kb) / KC;                           // chunks inside K
     const int64_t tail = CHECK ? 0 : (kfull < total ? kfull : total);  // first chunk crossing K
     if (tail > 0) load<false, 0>(0); else load<true, 0>(0);
     if (total > 1) { if (tail > 1) load<false, 1>(KC); else load<true, 1>(KC); }
@@ -451,7 +453,7 @@ struct Fused {
     else finish_any<0>(ps);
   }
 
-  __device__ __forceinline__ void write_c(PT *__restrict__ C) const {
+  __device__ __forceinline__ void write_c(PT *__restrict__ C, int64_t ldc) const {
 #pragma unroll
     for (int a = 0; a < RB; ++a)
 #pragma unroll
@@ -460,7 +462,7 @@ struct Fused {
         for (int r = 0; r < 4; ++r) {
           const int64_t row = r0 + wrow + (L96 ? 24 * lg + 4 * a : 16 * a + 4 * lg) + r;
           const int64_t col = c0 + wcol + 16 * b + lc;
-          if (row < pb.M && col < pb.N) C[row * pb.ldc + col] = accC[a][b][r];
+          if (row < pb.M && col < pb.N) C[row * ldc + col] = accC[a][b][r];
         }
   }
 };
@@ -468,76 +470,105 @@ struct Fused {
 template <typename IT, typename PT, int L, int FORM, bool TA, bool TB>
 __global__ __launch_bounds__(4 * L, (L == 64 ? 2 : 1)) void k_fused(GemmOperands g, const IT *__restrict__ A,
                                                  const IT *__restrict__ B, PT *__restrict__ C,
-                                                 int64_t ntiles, int64_t per_xcd) {
+                                                 PT *__restrict__ part, int64_t ntiles,
+                                                 int64_t ngroups, int64_t per_xcd) {
   typedef Fused<IT, PT, L, FORM, TA, TB> F;
   __shared__ typename F::Smem sm;
-  // XCD-aware tile order: workgroups are dealt to the 8 XCDs round-robin, so
-  // give each XCD a contiguous range, grouped a few tile-rows at a time so that
-  // the workgroups running together on one XCD share A panels and B slabs in
+  // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin, so give
+  // each XCD a contiguous range. Groups of the l-sum are the slowest index, so
+  // the workgroups running together on one XCD sum the same subblocks l; tiles
+  // go a few tile-rows at a time, so that they share A panels and B slabs in
   // that XCD's L2.
-  // A workgroup covers L rows and a 64-column slab; an inner kernel of L = 128
-  // is shared by two workgroups with the same pair settings.
+  // A workgroup covers L rows and a TN-column slab of one inner kernel.
   const int64_t bid = blockIdx.x;
   const int64_t lin = (bid & 7) * per_xcd + (bid >> 3);
-  if (lin >= ntiles) return;
+  if (lin >= ntiles * ngroups) return;
+  const int64_t grp_l = lin / ntiles;              // group of the l-sum
+  const int64_t tlin = lin - grp_l * ntiles;
   const Problem &pb = g.pb;
   constexpr int64_t SLABS = L / F::TN;
   const int64_t nS = pb.nJ * SLABS;
   constexpr int64_t GROUP = (L == 64) ? 8 : 4;    // tile rows per group: an XCD's
-  const int64_t grp = lin / (GROUP * nS);          // concurrent workgroups form a GROUP x 8 block
+  const int64_t grp = tlin / (GROUP * nS);         // concurrent workgroups form a GROUP x 8 block
   const int64_t first_i = grp * GROUP;
   const int64_t gsize = min(GROUP, pb.nI - first_i);
-  const int64_t in_grp = lin - grp * GROUP * nS;
+  const int64_t in_grp = tlin - grp * GROUP * nS;
   const int64_t ti = first_i + in_grp % gsize;
   const int64_t ts = in_grp / gsize;
   const int64_t tj = ts / SLABS;
+  const int64_t l0 = grp_l * g.gsize;
+  const int64_t nl = min(g.gsize, pb.nL - l0);
   F f(pb, A, B, sm, ti * L, ts * F::TN);
-  const tdgemm_pair *prs = g.pairs + (ti * pb.nJ + tj) * pb.nL;
+  f.kb = l0 * L;
+  const tdgemm_pair *prs = g.pairs + (ti * pb.nJ + tj) * pb.nL + l0;
   const bool interior = (ti + 1) * L <= pb.M && (ts + 1) * F::TN <= pb.N;
-  if (interior) f.template run<false>(prs);
-  else f.template run<true>(prs);
-  f.write_c(C);
+  if (interior) f.template run<false>(prs, nl);
+  else f.template run<true>(prs, nl);
+  if (ngroups > 1) f.write_c(part + grp_l * pb.M * pb.N, pb.N);
+  else f.write_c(C, pb.ldc);
+}
+
+// C = sum over the groups g (ascending, from zero) of their partial results.
+template <typename PT>
+__global__ __launch_bounds__(256) void k_sum_groups(const PT *__restrict__ part, int64_t ngroups,
+                                                    int64_t M, int64_t N, PT *__restrict__ C,
+                                                    int64_t ldc) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= M * N) return;
+  PT total = (PT)0;
+  for (int64_t q = 0; q < ngroups; ++q) total = total + part[q * M * N + e];
+  const int64_t r = e / N;
+  C[r * ldc + (e - r * N)] = total;
 }
 
 // ---------------------------------------------------------------------------
 template <typename IT, typename PT, int L, int FORM>
 static hipError_t launch_fused_t(const GemmOperands &g, const void *A, const void *B, void *C,
-                                 hipStream_t st) {
-  const int64_t ntiles = g.pb.nI * g.pb.nJ * (L / Fused<IT, PT, L, FORM, false, false>::TN);
-  const int64_t per_xcd = (ntiles + 7) / 8;
+                                 void *part, hipStream_t st) {
+  typedef Fused<IT, PT, L, FORM, false, false> F0;
+  const int64_t ntiles = g.pb.nI * g.pb.nJ * (L / F0::TN);
+  const int64_t ngroups = (g.pb.nL + g.gsize - 1) / g.gsize;
+  const int64_t per_xcd = (ntiles * ngroups + 7) / 8;
   const dim3 grid((unsigned)(per_xcd * 8));
-  const dim3 block(Fused<IT, PT, L, FORM, false, false>::NT);
+  const dim3 block(F0::NT);
   const IT *a = (const IT *)A;
   const IT *b = (const IT *)B;
   PT *c = (PT *)C;
+  PT *p = (PT *)part;
   if (!g.ta && !g.tb)
-    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, false, false>), grid, block, 0, st, g, a, b, c, ntiles, per_xcd);
+    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, false, false>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
   else if (g.ta && !g.tb)
-    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, true, false>), grid, block, 0, st, g, a, b, c, ntiles, per_xcd);
+    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, true, false>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
   else if (!g.ta && g.tb)
-    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, false, true>), grid, block, 0, st, g, a, b, c, ntiles, per_xcd);
+    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, false, true>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
   else
-    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, true, true>), grid, block, 0, st, g, a, b, c, ntiles, per_xcd);
+    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, true, true>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
+  if (ngroups > 1) {
+    const int64_t n = g.pb.M * g.pb.N;
+    hipLaunchKernelGGL((k_sum_groups<PT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, ngroups,
+                       g.pb.M, g.pb.N, c, g.pb.ldc);
+  }
   return hipGetLastError();
 }
 
 template <typename IT, typename PT>
 static hipError_t launch_fused_l(const GemmOperands &g, const void *A, const void *B, void *C,
-                                 hipStream_t st) {
+                                 void *part, hipStream_t st) {
   if (g.pb.L == 64)
-    return g.form == TDGEMM_SYM ? launch_fused_t<IT, PT, 64, TDGEMM_SYM>(g, A, B, C, st)
-                                : launch_fused_t<IT, PT, 64, TDGEMM_ASYM>(g, A, B, C, st);
+    return g.form == TDGEMM_SYM ? launch_fused_t<IT, PT, 64, TDGEMM_SYM>(g, A, B, C, part, st)
+                                : launch_fused_t<IT, PT, 64, TDGEMM_ASYM>(g, A, B, C, part, st);
   if (g.pb.L == 96)
-    return g.form == TDGEMM_SYM ? launch_fused_t<IT, PT, 96, TDGEMM_SYM>(g, A, B, C, st)
-                                : launch_fused_t<IT, PT, 96, TDGEMM_ASYM>(g, A, B, C, st);
-  return g.form == TDGEMM_SYM ? launch_fused_t<IT, PT, 128, TDGEMM_SYM>(g, A, B, C, st)
-                              : launch_fused_t<IT, PT, 128, TDGEMM_ASYM>(g, A, B, C, st);
+    return g.form == TDGEMM_SYM ? launch_fused_t<IT, PT, 96, TDGEMM_SYM>(g, A, B, C, part, st)
+                                : launch_fused_t<IT, PT, 96, TDGEMM_ASYM>(g, A, B, C, part, st);
+  return g.form == TDGEMM_SYM ? launch_fused_t<IT, PT, 128, TDGEMM_SYM>(g, A, B, C, part, st)
+                              : launch_fused_t<IT, PT, 128, TDGEMM_ASYM>(g, A, B, C, part, st);
 }
 
-hipError_t launch_fused(const GemmOperands &g, const void *A, const void *B, void *C, hipStream_t st) {
-  if (g.in_dtype == TDGEMM_F64 && g.prec == TDGEMM_F64) return launch_fused_l<double, double>(g, A, B, C, st);
-  if (g.in_dtype == TDGEMM_F32 && g.prec == TDGEMM_F64) return launch_fused_l<float, double>(g, A, B, C, st);
-  return launch_fused_l<float, float>(g, A, B, C, st);
+hipError_t launch_fused(const GemmOperands &g, const void *A, const void *B, void *C, void *part,
+                        hipStream_t st) {
+  if (g.in_dtype == TDGEMM_F64 && g.prec == TDGEMM_F64) return launch_fused_l<double, double>(g, A, B, C, part, st);
+  if (g.in_dtype == TDGEMM_F32 && g.prec == TDGEMM_F64) return launch_fused_l<float, double>(g, A, B, C, part, st);
+  return launch_fused_l<float, float>(g, A, B, C, part, st);
 }
 
 }  // namespace tdg

@@ -50,6 +50,7 @@ struct GemmOperands {
   int in_dtype, prec, form;
   bool ta, tb;
   const tdgemm_pair *pairs;   // [n_pairs]
+  int64_t gsize;              // subblocks per group of the l-sum (nL: one group)
 };
 
 hipError_t launch_stats(const StatsArgs &a, int dtype, int L, hipStream_t st);
@@ -66,7 +67,9 @@ hipError_t launch_unpack(const GemmOperands &g, const void *Rbar, void *r_int, v
                          hipStream_t st);
 
 // fused path
-hipError_t launch_fused(const GemmOperands &g, const void *A, const void *B, void *C, hipStream_t st);
+// part: partial results of the groups (ngroups x M x N of prec) when gsize < nL, else unused.
+hipError_t launch_fused(const GemmOperands &g, const void *A, const void *B, void *C, void *part,
+                        hipStream_t st);
 
 // Block-scaled INT8 / FP8 form (L = 128)
 struct Quant8Args {

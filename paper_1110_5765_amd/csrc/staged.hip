@@ -149,7 +149,9 @@ __global__ __launch_bounds__(kThreads) void k_unpack_pairs(GemmOperands g, const
   }
 }
 
-// Eq. (5) and the l-sum of eq. (2): C = sum_l r_l * inv_l, l ascending.
+// Eq. (5) and the l-sum of eq. (2): C = sum_l r_l * inv_l, l ascending, in
+// groups of gsize consecutive l (each from zero), the group sums added in
+// ascending order to zero.
 template <typename PT>
 __global__ __launch_bounds__(kThreads) void k_decompand_sum(GemmOperands g, const PT *Rbar, PT *C) {
   const Problem &pb = g.pb;
@@ -163,15 +165,19 @@ __global__ __launch_bounds__(kThreads) void k_decompand_sum(GemmOperands g, cons
   const int64_t i = tile / pb.nJ, j = tile - (tile / pb.nJ) * pb.nJ;
   const int64_t row = i * L + m, col = j * L + n;
   if (row >= pb.M || col >= pb.N) return;
-  PT acc = (PT)0;
+  PT sum = (PT)0, acc = (PT)0;
   for (int64_t l = 0; l < pb.nL; ++l) {
     const int64_t pair = (i * pb.nJ + j) * pb.nL + l;
     const tdgemm_pair o = g.pairs[pair];
     const PT r = unpack_one<PT>(Rbar + pair * L * L, m, n, L, o, g.form);
     const PT contrib = (o.w == 1) ? r : r * (PT)o.inv;
     acc = acc + contrib;
+    if ((l + 1) % g.gsize == 0 || l + 1 == pb.nL) {
+      sum = sum + acc;
+      acc = (PT)0;
+    }
   }
-  C[row * pb.ldc + col] = acc;
+  C[row * pb.ldc + col] = sum;
 }
 
 // C = 0 (an empty inner dimension).

@@ -37,7 +37,7 @@ class Desc(ctypes.Structure):
                 ("fixed_w", ctypes.c_int32), ("snr_db", ctypes.c_double),
                 ("fixed_rmax", ctypes.c_double), ("sep_q", ctypes.c_double),
                 ("u_safe", ctypes.c_double), ("accel", ctypes.c_double),
-                ("tile_target", ctypes.c_void_p)]
+                ("tile_target", ctypes.c_void_p), ("k_split", ctypes.c_int32)]
 
 
 class Calib(ctypes.Structure):
@@ -150,7 +150,7 @@ def make_desc(A: torch.Tensor, B: torch.Tensor, *, L: int = 64, form: str = "sym
               prec: str | None = None, ctrl: str = "snr", snr_db: float = 40.0,
               w_allowed=(1, 2, 4), fixed_w: int = 2, fixed_rmax: float = float(2 ** 20),
               sep_q: float = 127.0, u_safe: float = 50.0, accel: float = 1.0,
-              ldc: int | None = None, tile_target=None) -> Desc:
+              ldc: int | None = None, tile_target=None, k_split: int = 1) -> Desc:
     M, K = A.shape
     K2, N = B.shape
     if K != K2:
@@ -176,6 +176,7 @@ def make_desc(A: torch.Tensor, B: torch.Tensor, *, L: int = 64, form: str = "sym
     d.sep_q = sep_q
     d.u_safe = u_safe
     d.accel = accel
+    d.k_split = k_split
     if tile_target is not None:
         # host array nI x nJ of per-inner-kernel targets (S in dB or F_kernel); the
         # descriptor keeps it alive for tdgemm_plan
@@ -186,6 +187,16 @@ def make_desc(A: torch.Tensor, B: torch.Tensor, *, L: int = 64, form: str = "sym
         d._tile_keep = t
         d.tile_target = t.ctypes.data
     return d
+
+
+def auto_k_split(M: int, N: int, K: int, L: int, workgroups: int = 512) -> int:
+    """A k_split that gives about `workgroups` fused workgroups when M and N leave
+    few inner kernels (1 when they are enough). Only the order of the l-sum
+    changes, in the way tdgemm_desc.k_split describes."""
+    nI, nJ, nL = -(-M // L), -(-N // L), -(-K // L)
+    if nL <= 1:
+        return 1
+    return max(1, min(nL, -(-workgroups // max(1, nI * nJ))))
 
 
 def torch_dtype(prec_code: int) -> torch.dtype:

@@ -101,6 +101,7 @@ def _desc(binding, **kw):
     ({"ctrl": 2, "sep_q": 0.5}, -1), ({"u_safe": 0.0}, -1), ({"K": 64 * 513, "lda": 64 * 513}, -2),
     ({"ctrl": 4}, 0), ({"ctrl": 4, "snr_db": -math.inf}, -1), ({"ctrl": 4, "fixed_rmax": -1.0}, -1),
     ({"ctrl": 4, "fixed_w": 3}, -1), ({"ctrl": 4, "snr_db": math.inf}, 0),
+    ({"k_split": -1}, -1), ({"k_split": 3}, 0), ({"k_split": 1000}, 0),
 ])
 def test_descriptor_validation(binding, lib, kw, status):
     d = _desc(binding, **kw)
@@ -185,3 +186,15 @@ def test_matrix_layout_detection(binding):
     assert binding.matrix_layout(Y) == (0, 10)
     with pytest.raises(ValueError):
         binding.matrix_layout(torch.zeros(4, 6)[:, ::2])
+
+
+def test_k_split_workspace(binding, lib):
+    """A split l-sum keeps ceil(nL / s) partial M x N results in the workspace."""
+    size = lib.tdgemm_workspace_size
+    size.restype = ctypes.c_size_t
+    d1 = _desc(binding, K=64 * 10, lda=64 * 10)
+    d4 = _desc(binding, K=64 * 10, lda=64 * 10, k_split=4)          # groups of 3: 4 groups
+    extra = size(ctypes.byref(d4)) - size(ctypes.byref(d1))
+    assert 4 * 256 * 256 * 8 <= extra < 4 * 256 * 256 * 8 + 512
+    d8 = _desc(binding, prec=binding.I8, ctrl=binding.CTRL_SEPARABLE, fixed_w=1, L=128, k_split=2)
+    assert size(ctypes.byref(d8)) == 0

@@ -193,3 +193,50 @@ def test_calibration_parity(td, form, prec, W, L):
             assert s[t] == so and m[t] == mo, (q, s[t], so, m[t], mo)
     log(f"[calib] {form} {prec} W={W} L={L}: {len(qs)} points equal; first nonzero s at R="
         f"{next((x for x, y in zip(r, s) if y > 0), None)}")
+
+
+SPLIT_CASES = [
+    # name, M, K, N, L, form, prec, k_split, ta, tb
+    ("split3_sym_L64", 130, 64 * 11 + 5, 150, 64, "sym", "f64", 3, 0, 0),
+    ("split4_asym_L128_ta", 200, 128 * 9, 70, 128, "asym", "f64", 4, 1, 0),
+    ("split5_sym_L96_f32", 96, 96 * 13 + 40, 100, 96, "sym", "f32", 5, 0, 1),
+    ("split_all_asym_L96", 100, 96 * 6, 96, 96, "asym", "f64", 64, 0, 0),
+]
+
+
+@pytest.mark.parametrize("case", SPLIT_CASES, ids=[c[0] for c in SPLIT_CASES])
+def test_k_split_parity(td, case):
+    """The l-sum of eq. (2) in groups of consecutive subblocks (k_split): the fused
+    kernel with one workgroup per group plus the ordered group sum equals the staged
+    path bit for bit, and the oracle with the same grouping within the stated bound."""
+    name, M, K, N, L, form, prec, ks, ta, tb = case
+    log(f"[split] {name}: M={M} K={K} N={N} L={L} {form} {prec} k_split={ks}")
+    dt = np.float64 if prec == "f64" else np.float32
+    A, B, Ad, Bd = _inputs(M, K, N, dt, ta, tb, seed=zlib.crc32(name.encode()))
+    wal = (1, 2, 3) if L == 96 else (1, 2, 4)
+    if prec == "f32":
+        wal = (1, 2)
+    snr = 40.0 if prec == "f64" else 15.0
+    calib, tabs = device_calib(td, L, form, prec, tuple(w for w in wal if w > 1))
+    cfg = oracle_cfg(L, form, prec, "snr", snr, wal, 2, 1.0, 127.0)
+    import dataclasses
+    ref = pl.run(A, B, dataclasses.replace(cfg, k_groups=ks), calib=tabs)
+    desc = td.make_desc(Ad, Bd, L=L, form=form, prec=prec, ctrl="snr", snr_db=snr, w_allowed=wal,
+                        k_split=ks)
+    plan = td.tdgemm_plan(desc, Ad, Bd, calib)
+    pt = td.torch_dtype(desc.prec)
+    n = td.slot_elems(plan)
+    bufs = {k: torch.empty((n,), dtype=pt, device="cuda") for k in ("qA", "qB", "pA", "pB", "R")}
+    C_st = torch.full((M, N), float("nan"), dtype=pt, device="cuda")
+    C_fu = torch.full((M, N), float("nan"), dtype=pt, device="cuda")
+    td.tdgemm_compand(plan, Ad, Bd, bufs["qA"], bufs["qB"])
+    td.tdgemm_pack(plan, bufs["qA"], bufs["qB"], bufs["pA"], bufs["pB"])
+    td.tdgemm_gemm(plan, bufs["pA"], bufs["pB"], bufs["R"], fused=0)
+    td.tdgemm_unpack(plan, bufs["R"], None, C_st)
+    td.tdgemm_gemm(plan, Ad, Bd, C_fu, fused=1)
+    torch.cuda.synchronize()
+    Cs, Cf = C_st.cpu().numpy(), C_fu.cpu().numpy()
+    assert np.all(np.isfinite(Cf))
+    np.testing.assert_array_equal(Cf, Cs)
+    assert rel_err(Cf, ref.C) <= TOL[prec]
+    log(f"[split] {name}: C rel err {rel_err(Cf, ref.C):.3e} (bit-exact: {np.array_equal(Cf, ref.C)})")

@@ -4,7 +4,8 @@ The image scatter matrix G = sum_j A_j^T A_j (one product over the stacked
 training images, A^T passed as a transposed view) and the projections Y = A X
 run through the library with FP32 packing at L = 96 and are compared with the
 oracle on the same inputs; X comes from the oracle's G, so both sides project
-onto the same axes. Bar: relative Frobenius error <= 1e-5 (FP32 packing), and
+onto the same axes. G sums its 12 subblocks in groups (auto_k_split), as the
+bench does. Bar: relative Frobenius error <= 1e-5 (FP32 packing), and
 the nearest-neighbour matches of the two sides agree.
 """
 import numpy as np
@@ -38,8 +39,12 @@ def test_pca2d_gemms(td, snr):
     calib, tabs = device_calib(td, L, "sym", "f32", (2,))
     cfg = oracle_cfg(L, "sym", "f32", "snr", snr, (1, 2), 2, 1.0, 127.0)
 
+    def ks(A, B):
+        return td.auto_k_split(A.shape[0], B.shape[1], A.shape[1], L)
+
     def lib(A, B):
-        desc = td.make_desc(A, B, L=L, form="sym", prec="f32", ctrl="snr", snr_db=snr, w_allowed=(1, 2))
+        desc = td.make_desc(A, B, L=L, form="sym", prec="f32", ctrl="snr", snr_db=snr, w_allowed=(1, 2),
+                            k_split=ks(A, B))
         plan = td.tdgemm_plan(desc, A, B, calib)
         C = torch.empty((A.shape[0], B.shape[1]), dtype=torch.float32, device="cuda")
         td.tdgemm_gemm(plan, A, B, C, fused=1)
@@ -47,14 +52,16 @@ def test_pca2d_gemms(td, snr):
         return C.cpu().numpy()
 
     Sd, Td = to_dev(S), to_dev(T)
-    G_ref = pl.run(np.ascontiguousarray(S.T), S, cfg, calib=tabs).C
+    import dataclasses
+    G_ref = pl.run(np.ascontiguousarray(S.T), S, dataclasses.replace(cfg, k_groups=ks(Sd.t(), Sd)),
+                   calib=tabs).C
     G = lib(Sd.t(), Sd)
     assert rel_err(G, G_ref) <= 1e-5
     _, V = np.linalg.eigh(G_ref.astype(np.float64))
     X = np.ascontiguousarray(V[:, ::-1][:, :d]).astype(np.float32)
     Xd = to_dev(X)
-    Ys_ref = pl.run(S, X, cfg, calib=tabs).C
-    Yt_ref = pl.run(T, X, cfg, calib=tabs).C
+    Ys_ref = pl.run(S, X, dataclasses.replace(cfg, k_groups=ks(Sd, Xd)), calib=tabs).C
+    Yt_ref = pl.run(T, X, dataclasses.replace(cfg, k_groups=ks(Td, Xd)), calib=tabs).C
     Ys, Yt = lib(Sd, Xd), lib(Td, Xd)
     assert rel_err(Ys, Ys_ref) <= 1e-5 and rel_err(Yt, Yt_ref) <= 1e-5
 

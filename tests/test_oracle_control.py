@@ -334,3 +334,23 @@ def test_target_control_meets_the_subblock_snr():
         got[S] = pl.snr_db(pl.run(A, B, cfg, calib=calib).C, ref)
     assert abs(got[25.0] - 25.0) < 1.0 and abs(got[40.0] - 40.0) < 1.0, got
     assert 40.0 < got[70.0] < 50.0, got          # beyond reach: the best R_max = 2^22 allows
+
+
+def test_grouped_l_sum():
+    """The l-sum of eq. (2) in groups of consecutive subblocks: one group is the plain
+    ascending sum bit for bit; any grouping stays within FP64 rounding of it and every
+    group size is ceil(nL / k_groups)."""
+    rng = np.random.default_rng(61)
+    A = rng.standard_normal((96, 64 * 9))
+    B = rng.laplace(0.0, 1.0, (64 * 9, 80))
+    calib = {W: tables(64, "sym", "f64", (2, 4))[W] for W in (2, 4)}
+    cfg = pl.Config(L=64, form="sym", ctrl="snr", snr_db=30.0, w_allowed=(1, 2, 4))
+    plan = pl.make_plan(A, B, cfg, calib)
+    one = pl.run(A, B, cfg, calib, plan=plan).C
+    assert np.array_equal(pl.run(A, B, dataclasses.replace(cfg, k_groups=1), calib, plan=plan).C, one)
+    for G, size in ((2, 5), (3, 3), (4, 3), (9, 1), (20, 1)):
+        assert pl.group_size(9, G) == size
+        got = pl.run(A, B, dataclasses.replace(cfg, k_groups=G), calib, plan=plan).C
+        assert np.max(np.abs(got - one)) <= 1e-12 * np.max(np.abs(one))
+    with pytest.raises(ValueError):
+        pl.group_size(9, 0)
