@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-k-split", dest="k_split", action="store_false",
-                    help="pca2d: one workgroup per inner kernel (no grouped l-sum)")
+                    help="pca2d, scatter: one workgroup per inner kernel (no grouped l-sum)")
     ap.add_argument("--workload", default="sweep",
                     choices=["sweep", "precision", "mlp", "scatter", "sweep-table", "fig7", "pca2d"])
     ap.add_argument("--mlp-steps", type=int, default=200)
@@ -800,8 +800,9 @@ def run_scatter(args):
         ref = torch.matmul(A.double(), B.double())
         res[name] = {"M": M, "N": N, "K": K}
         for S in (50.0, 40.0, 20.0):
+            ks = td.auto_k_split(M, N, K, L) if args.k_split else 1
             desc = td.make_desc(A, B, L=L, form=args.form, prec="f64", ctrl="snr", snr_db=S,
-                                w_allowed=(1, 2, 4))
+                                w_allowed=(1, 2, 4), k_split=ks)
             ws = torch.empty(td.tdgemm_workspace_size(desc), dtype=torch.uint8, device="cuda")
             C = torch.empty((M, N), dtype=torch.float64, device="cuda")
             holder = {}
@@ -819,7 +820,7 @@ def run_scatter(args):
             wh = {int(w): int((pairs["w"] == w).sum()) for w in (1, 2, 4)}
             snr = snr_of(torch, C, ref)
             res[name][f"S{S:g}"] = {"ms": round(ms, 4), "gflops": round(flops / ms / 1e6, 1),
-                                    "snr_db": round(snr, 2), "w_histogram": wh}
+                                    "snr_db": round(snr, 2), "w_histogram": wh, "k_split": ks}
             log(f"[bench] {name} ({M}x{K} by {K}x{N}) S={S:g}: {ms:.3f} ms -> {flops / ms / 1e6:.1f} "
                 f"effective GFLOP/s at {snr:.2f} dB, W {wh}")
         A64, B64 = A.double(), B.double()
