@@ -234,7 +234,7 @@ def run_sweep(args):
 
     # accuracy and plan summary (outside the timed region)
     sa, sb, pairs, budget = td.tdgemm_plan_export(plan)
-    wh = {int(w): int((pairs["w"] == w).sum()) for w in (1, 2, 4)}
+    wh = {int(w): int((pairs["w"] == w).sum()) for w in ws_allowed}
     ref = torch.matmul(Ad, Bd)
     snr = snr_of(torch, C, ref)
     L = args.L

@@ -102,7 +102,9 @@ struct Fused {
   static constexpr bool A_QUAD = FORM == TDGEMM_SYM && !TA;
   static constexpr bool A_SPLIT = A_QUAD && VA == 8;
   static constexpr int koffA(int v) { return A_SPLIT ? (v % 4) + 16 * (v / 4) : v; }
-  static constexpr int PF = 2;            // register sets of raw loads (chunks g+1, g+2)
+  // register sets of raw loads: the prefetch distance in chunks (one at L = 96,
+  // where the six row blocks per wavefront leave fewer registers)
+  static constexpr int PF = L96 ? 1 : 2;
   typedef typename Mfma<PT>::Acc Acc;
   static_assert(VA * NT == KC * L && VB * NT == KC * TN, "loads must cover a chunk");
   static_assert(KC % (4 * WMAX) == 0 && KC % 8 == 0, "packed chunk depth: whole k-steps");
@@ -402,7 +404,7 @@ struct Fused {
     lds_barrier();
     // always issued (the last chunk again past the end), so that the number of
     // loads in flight is the same on every path and waits count exactly
-    const int64_t g2 = g + 2 < total ? g + 2 : total - 1;
+    const int64_t g2 = g + PF < total ? g + PF : total - 1;
     load<CHECK, S>((g2 / NCH) * L + (g2 % NCH) * KC);
     if (NACC == 1 && finish_prev) finish_any<0>(prev);
     mma_any<P>(buf, ps.w);
@@ -417,11 +419,11 @@ struct Fused {
     ps = pair_state(prs[l]);
     const int64_t g0 = l * NCH;
     iter<CHECK, 0, P>(g0, total, ps, prev, l > 0);
-    iter<CHECK, 1, P>(g0 + 1, total, ps, prev, false);
+    iter<CHECK, PF - 1, P>(g0 + 1, total, ps, prev, false);
 #pragma unroll 1
     for (int kc = 2; kc < NCH; kc += 2) {
       iter<CHECK, 0, P>(g0 + kc, total, ps, prev, false);
-      iter<CHECK, 1, P>(g0 + kc + 1, total, ps, prev, false);
+      iter<CHECK, PF - 1, P>(g0 + kc + 1, total, ps, prev, false);
     }
   }
 
@@ -434,9 +436,9 @@ struct Fused {
     const int64_t kfull = (pb.K - kb) / KC;                           // chunks inside K
     const int64_t tail = CHECK ? 0 : (kfull < total ? kfull : total);  // first chunk crossing K
     if (tail > 0) load<false, 0>(0); else load<true, 0>(0);
-    if (total > 1) { if (tail > 1) load<false, 1>(KC); else load<true, 1>(KC); }
+    if (PF == 2 && total > 1) { if (tail > 1) load<false, PF - 1>(KC); else load<true, PF - 1>(KC); }
     // pair l prefetches up to chunk (l + 1) NCH + 1
-    int64_t l1 = tail >= 2 ? (tail - 2) / NCH : 0;
+    int64_t l1 = tail >= PF ? (tail - PF) / NCH : 0;
     l1 -= l1 & 1;
     PairState ps = pair_state(prs[0]), prev = ps;
     int64_t l = 0;
