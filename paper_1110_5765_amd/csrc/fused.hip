@@ -89,10 +89,13 @@ struct Fused {
   // MFMAs; with one (L = 96, six row blocks per wavefront) the unpack runs
   // before them
   static constexpr int NACC = L96 ? 1 : 2;
-  // LDS row strides in elements: with an odd A stride the 16 rows read by one
-  // group of 16 lanes fall on distinct bank pairs.
-  static constexpr int SA = KC + 1;
-  static constexpr int SB = TN + 1;
+  // LDS row strides in elements. A 64-bit fragment read serves 32 lanes at a
+  // time over 64 four-byte banks: lane groups g = 0, 1 read rows lc = 0..15 at
+  // column g (A) or column lc of rows g (B). With SA = KC + 2 (2 mod 32) the 32
+  // A reads start on distinct even banks; with SB = TN + 16 (16 mod 32) the two
+  // B rows fall on opposite halves of the banks.
+  static constexpr int SA = KC + 2;
+  static constexpr int SB = TN + 16;
   static constexpr int NCH = L / KC;      // chunks per pair
   // Symmetric form, A stored as given: four consecutive threads share a row and
   // thread i of the four holds columns 4i..4i+3 (and 4i+16..4i+19 when a chunk
