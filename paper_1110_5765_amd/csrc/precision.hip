@@ -112,8 +112,10 @@ __global__ __launch_bounds__(kThreads) void k_quant8(Quant8Args a) {
 // (INT8 16x16x64 with exact INT32 results; FP8 16x16x128 with FP32 results),
 // and then either written out per pair (STAGED) or added to C as
 // float(r) * float(inv), l ascending.
+// At most 256 registers per lane, so that two workgroups (72 KB of LDS each)
+// share a CU and one's LDS waits and epilogue overlap the other's MFMAs.
 template <int FMT, bool STAGED>
-__global__ __launch_bounds__(kThreads) void k_gemm8(Gemm8Args a) {
+__global__ __launch_bounds__(kThreads, 2) void k_gemm8(Gemm8Args a) {
   __shared__ __align__(16) uint8_t sa[2][kL8][kRow8];
   __shared__ __align__(16) uint8_t sb[2][kL8][kRow8];
   const int64_t tile = blockIdx.x;
