@@ -1,30 +1,32 @@
 // Fused throughput-distortion GEMM: every stage of a subblock pair in one
 // kernel (Sec. 3 with the settings of Sec. 5.B / Sec. 6).
 //
-// One workgroup (L / 16 wavefronts) computes one L x L inner kernel R_ij and
-// walks its pairs l = 0, 1, ... in order. Each pair's K extent is cut into
-// chunks of 32 raw columns. For every chunk the threads load raw A / B values
-// from HBM (the next chunk's loads are in flight while the current one is
-// multiplied), compand them (eq. 3) and pack them (eqs. 6-7, or 11) straight
-// into a double-buffered LDS tile; each wavefront then runs FP64 (or FP32)
-// 16x16x4 MFMAs for its 64-row x (L/4)-column part of the tile, accumulating
-// the packed product over the packed index in ascending order. After a pair's last chunk the packed
-// result is unpacked in registers (eqs. 9-10 or 13-14), reverse-companded
-// (eq. 5) and added to a register-resident C tile (eq. 2). W = 1 pairs run the
-// plain product. C is written once at the end.
+// A workgroup computes an L x TN slab of one inner kernel R_ij (TN = 64 at
+// L = 64 and 128, 96 at L = 96) and walks its pairs l in ascending order --
+// all of them, or one group of consecutive l when the l-sum is split (the
+// group sums are then added in order by k_sum_groups). Each pair's K extent is
+// cut into chunks of KC raw columns (16, 24 or 32). For every chunk the threads
+// load raw A / B values from HBM one or two chunks ahead, compand them (eq. 3)
+// and pack them (eqs. 6-7, or 11) into a double-buffered LDS tile; each
+// wavefront then runs FP64 (or FP32) 16x16x4 MFMAs for its 16 RB x 16 part of
+// the tile, accumulating the packed product over the packed index in ascending
+// order. After a pair's last chunk the packed result is unpacked in registers
+// (eqs. 9-10 or 13-14), reverse-companded (eq. 5) and added to a
+// register-resident C tile (eq. 2). W = 1 pairs run the plain product. C (or
+// the group's partial result) is written once at the end.
 //
-// Row placement: lane (g = lane / 16, c = lane % 16) of the wavefront owning
-// rows 64 wr.. keeps, for its row block rb and register r, the C element of tile
-// row 64 wr + 16 rb + 4 g + r. The LDS row of the
-// A operand that feeds that result slot is permuted accordingly, which for the
-// asymmetric form also routes the W rows unpacked from one packed word to the
-// same lane whatever the pair's W.
+// Row placement: lane (g = lane / 16, c = lane % 16) keeps, for its row block
+// a and register r, the C element of tile row 16 a + 4 g + r of its wavefront
+// (L = 64, 128) or 24 g + 4 a + r (L = 96). The LDS row of the A operand that
+// feeds that result slot is permuted accordingly, which for the asymmetric
+// form also routes the W rows unpacked from one packed word to the same lane
+// whatever the pair's W.
 //
-// Thread layout of the raw loads (NT = 4 L threads, 8 values per thread and
-// operand per chunk), independent of W so that prefetching may cross pairs:
-//   A, symmetric form:  one row, 8 consecutive columns (packs along columns);
-//   A, asymmetric form: one column, 8 consecutive rows (packs along rows);
-//   B:                  one column, 8 consecutive rows.
+// Thread layout of the raw loads (VA / VB values per thread and operand per
+// chunk), independent of W so that prefetching may cross pairs:
+//   A, symmetric form:  one row, consecutive columns (packs along columns);
+//   A, asymmetric form: one column, consecutive rows (packs along rows);
+//   B:                  one column, consecutive rows.
 #include <type_traits>
 
 #include "common.h"
@@ -394,11 +396,11 @@ struct Fused {
   }
 
   // Chunk g of the pair in accumulator set P: compand + pack register set S
-  // into LDS buffer g % 2, barrier, issue the raw loads of chunk g + 2 into set
-  // S (two chunks of matrix work before they are needed), run chunk g's MFMAs.
-  // In the first chunk of a pair the previous pair (set 1 - P) is unpacked
-  // right after these MFMAs are issued, so the vector ALU unpacks while the
-  // matrix cores work.
+  // into LDS buffer g % 2, barrier, issue the raw loads of chunk g + PF into
+  // set S (PF chunks of matrix work before they are needed), run chunk g's
+  // MFMAs. In the first chunk of a pair the previous pair is unpacked: with two
+  // accumulator sets right after these MFMAs are issued (set 1 - P; measured
+  // faster than unpacking first), with one before them.
   template <bool CHECK, int S, int P>
   __device__ __forceinline__ void iter(int64_t g, int64_t total, const PairState &ps,
                                        const PairState &prev, bool finish_prev) {
@@ -440,7 +442,7 @@ struct Fused {
     const int64_t tail = CHECK ? 0 : (kfull < total ? kfull : total);  // first chunk crossing K
     if (tail > 0) load<false, 0>(0); else load<true, 0>(0);
     if (PF == 2 && total > 1) { if (tail > 1) load<false, PF - 1>(KC); else load<true, PF - 1>(KC); }
-    // pair l prefetches up to chunk (l + 1) NCH + 1
+    // pair l prefetches up to chunk (l + 1) NCH + PF - 1
     int64_t l1 = tail >= PF ? (tail - PF) / NCH : 0;
     l1 -= l1 & 1;
     PairState ps = pair_state(prs[0]), prev = ps;
