@@ -33,6 +33,7 @@ class TDConfig:
     fixed_rmax: float = float(2 ** 20)
     sep_q: float = 127.0
     min_dim: int = 128          # products with a smaller M, N or K stay plain (torch)
+    k_split: int | None = None  # groups of the l-sum per product; None: auto_k_split
 
 
 class TDContext:
@@ -62,9 +63,10 @@ class TDContext:
         if min(M, N, K) < c.min_dim:
             self.plain_calls += 1
             return A @ B
+        ks = td.auto_k_split(M, N, K, c.L) if c.k_split is None else c.k_split
         desc = td.make_desc(A, B, L=c.L, form=c.form, prec=c.prec, ctrl=c.ctrl, snr_db=c.snr_db,
                             w_allowed=c.w_allowed, fixed_w=c.fixed_w, fixed_rmax=c.fixed_rmax,
-                            sep_q=c.sep_q)
+                            sep_q=c.sep_q, k_split=ks)
         ws = self.workspace(desc, A.device)
         plan = td.tdgemm_plan(desc, A, B, self.calib if c.ctrl in ("snr", "accel", "target") else None, ws)
         out = torch.empty((M, N), dtype=td.torch_dtype(desc.prec), device=A.device)
