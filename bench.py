@@ -109,8 +109,8 @@ def calibrate_gpu(td, torch, L, form, prec, ws):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(the sharded design is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: tdgemm runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the product would shard by inner kernel, one C panel per GPU)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
