@@ -240,3 +240,21 @@ def test_k_split_parity(td, case):
     np.testing.assert_array_equal(Cf, Cs)
     assert rel_err(Cf, ref.C) <= TOL[prec]
     log(f"[split] {name}: C rel err {rel_err(Cf, ref.C):.3e} (bit-exact: {np.array_equal(Cf, ref.C)})")
+
+
+def test_calibration_table_cache(td, tmp_path, monkeypatch):
+    """A table measured on the GPU and stored is read back bit for bit, without measuring."""
+    from paper_1110_5765_amd import calib
+    p = str(tmp_path / "calib_L64_sym_f64.json")
+    _, r, table = calib.device_table(64, "sym", "f64", (2, 4), cache=p)
+
+    def no_measure(*a, **k):
+        raise AssertionError("measured although a matching table is stored")
+
+    monkeypatch.setattr(calib.td, "tdgemm_calibrate", no_measure)
+    dev, r2, t2 = calib.device_table(64, "sym", "f64", (2, 4), cache=p)
+    assert np.asarray(r2).tobytes() == np.asarray(r, dtype=np.float64).tobytes()
+    for W in (2, 4):
+        assert t2[W].tobytes() == np.asarray(table[W], dtype=np.float64).tobytes()
+    s = dev.s.cpu().numpy().reshape(3, -1)
+    assert s[0].tobytes() == t2[2].tobytes() and s[2].tobytes() == t2[4].tobytes()
