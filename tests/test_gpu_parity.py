@@ -258,3 +258,48 @@ def test_calibration_table_cache(td, tmp_path, monkeypatch):
         assert t2[W].tobytes() == np.asarray(table[W], dtype=np.float64).tobytes()
     s = dev.s.cpu().numpy().reshape(3, -1)
     assert s[0].tobytes() == t2[2].tobytes() and s[2].tobytes() == t2[4].tobytes()
+
+
+LDC_CASES = [
+    # name, M, K, N, L, form, in/pack precision, k_split
+    ("ldc_sym_L64", 130, 200, 150, 64, "sym", "f64", 1),
+    ("ldc_asym_L128_split3", 200, 128 * 5, 70, 128, "asym", "f64", 3),
+    ("ldc_sym_L96_f32", 100, 250, 90, 96, "sym", "f32", 1),
+]
+
+
+@pytest.mark.parametrize("case", LDC_CASES, ids=[c[0] for c in LDC_CASES])
+def test_ldc_wider_than_n(td, case):
+    """C written with a leading dimension above N: the M x N part equals the
+    ldc = N result bit for bit (fused and staged), the padding stays untouched."""
+    name, M, K, N, L, form, prec, ks = case
+    log(f"[parity] {name}: M={M} K={K} N={N} L={L} {form} {prec} k_split={ks}, ldc={N + 37}")
+    dt = np.float64 if prec == "f64" else np.float32
+    A, B, Ad, Bd = _inputs(M, K, N, dt, 0, 0, seed=zlib.crc32(name.encode()))
+    wal = (1, 2) if prec == "f32" else ((1, 2, 3) if L == 96 else (1, 2, 4))
+    calib, _ = device_calib(td, L, form, prec, tuple(w for w in wal if w > 1))
+    snr = 30.0 if prec == "f64" else 12.0
+    pt = torch.float64 if prec == "f64" else torch.float32
+    ldc = N + 37
+    d0 = td.make_desc(Ad, Bd, L=L, form=form, prec=prec, ctrl="snr", snr_db=snr, w_allowed=wal, k_split=ks)
+    d1 = td.make_desc(Ad, Bd, L=L, form=form, prec=prec, ctrl="snr", snr_db=snr, w_allowed=wal, k_split=ks,
+                      ldc=ldc)
+    p0 = td.tdgemm_plan(d0, Ad, Bd, calib)
+    p1 = td.tdgemm_plan(d1, Ad, Bd, calib)
+    C0 = torch.full((M, N), float("nan"), dtype=pt, device="cuda")
+    C1 = torch.full((M, ldc), 12345.0, dtype=pt, device="cuda")
+    C2 = torch.full((M, ldc), -777.0, dtype=pt, device="cuda")
+    td.tdgemm_gemm(p0, Ad, Bd, C0, fused=1)
+    td.tdgemm_gemm(p1, Ad, Bd, C1, fused=1)
+    n = td.slot_elems(p1)
+    bufs = [torch.empty(n, dtype=pt, device="cuda") for _ in range(5)]
+    td.tdgemm_compand(p1, Ad, Bd, bufs[0], bufs[1])
+    td.tdgemm_pack(p1, bufs[0], bufs[1], bufs[2], bufs[3])
+    td.tdgemm_gemm(p1, bufs[2], bufs[3], bufs[4], fused=0)
+    td.tdgemm_unpack(p1, bufs[4], None, C2)
+    torch.cuda.synchronize()
+    c0, c1, c2 = C0.cpu().numpy(), C1.cpu().numpy(), C2.cpu().numpy()
+    assert np.all(np.isfinite(c0))
+    assert c1[:, :N].tobytes() == np.ascontiguousarray(c0).tobytes()
+    assert c2[:, :N].tobytes() == np.ascontiguousarray(c0).tobytes()
+    assert np.all(c1[:, N:] == 12345.0) and np.all(c2[:, N:] == -777.0)
