@@ -303,3 +303,38 @@ def test_ldc_wider_than_n(td, case):
     assert c1[:, :N].tobytes() == np.ascontiguousarray(c0).tobytes()
     assert c2[:, :N].tobytes() == np.ascontiguousarray(c0).tobytes()
     assert np.all(c1[:, N:] == 12345.0) and np.all(c2[:, N:] == -777.0)
+
+
+@pytest.mark.parametrize("form,L,ta,tb", [("sym", 64, 0, 0), ("asym", 128, 1, 0), ("sym", 96, 0, 1)])
+def test_padded_operands(td, form, L, ta, tb):
+    """A and B as slices of wider matrices (lda, ldb above the stored row length):
+    plan and C equal those of contiguous copies bit for bit."""
+    M, K, N = 150, 260, 110
+    log(f"[parity] padded operands: {form} L={L} ta={ta} tb={tb}")
+    rng = np.random.default_rng(L + 7 * ta + 13 * tb)
+    A = rng.standard_normal((M, K))
+    B = rng.laplace(0.0, 1.0, (K, N))
+
+    def padded(X, t):
+        if t:   # stored transposed, K x M (or N x K) rows padded by 9
+            big = torch.full((X.shape[1], X.shape[0] + 9), float("nan"), dtype=torch.float64, device="cuda")
+            big[:, :X.shape[0]] = to_dev(X.T.copy())
+            return big[:, :X.shape[0]].t()
+        big = torch.full((X.shape[0], X.shape[1] + 5), float("nan"), dtype=torch.float64, device="cuda")
+        big[:, :X.shape[1]] = to_dev(X)
+        return big[:, :X.shape[1]]
+
+    Ap, Bp = padded(A, ta), padded(B, tb)
+    Ac, Bc = to_dev(A), to_dev(B)
+    wal = (1, 2, 3) if L == 96 else (1, 2, 4)
+    calib, _ = device_calib(td, L, form, "f64", tuple(w for w in wal if w > 1))
+    outs = []
+    for a, b in ((Ac, Bc), (Ap, Bp)):
+        d = td.make_desc(a, b, L=L, form=form, ctrl="snr", snr_db=30.0, w_allowed=wal)
+        p = td.tdgemm_plan(d, a, b, calib)
+        C = torch.full((M, N), float("nan"), dtype=torch.float64, device="cuda")
+        td.tdgemm_gemm(p, a, b, C, fused=1)
+        torch.cuda.synchronize()
+        outs.append((td.tdgemm_plan_export(p)[2], C.cpu().numpy()))
+    assert outs[0][0].tobytes() == outs[1][0].tobytes()
+    assert np.all(np.isfinite(outs[0][1])) and outs[0][1].tobytes() == outs[1][1].tobytes()
