@@ -220,6 +220,21 @@ tdgemm_status tdgemm_gemm(tdgemm_plan_t plan, const void *a, const void *b, void
 tdgemm_status tdgemm_unpack(tdgemm_plan_t plan, const void *Rbar, void *r_int, void *C,
                             void *stream);
 
+/* Summary of a plan (Sec. 6 and Prop. 3). Synchronises the stream the plan was
+ * made on, then reads its statistics and pair records. Any pointer may be NULL.
+ *  pred_snr_db  predicted output SNR of C in dB: 10 log10 of the sum over all
+ *               pairs of the signal power L_eff sigma_a^2 sigma_b^2 (block RMS
+ *               values, L_eff the valid inner extent) over the sum of their
+ *               expected noise powers D (eq. 21); +inf when every D is 0 (all
+ *               native, or an empty product).
+ *  w_hist       5 counters: w_hist[W] = pairs at packing W (W = 1..4); w_hist[0] = 0.
+ *  n_short      TARGET control: pairs at W >= 2 whose expected SNR (signal / D)
+ *               is below their target (eq. 25 fails there and the eq. (26)
+ *               companders, the best at fixed_rmax, are used); 0 otherwise.
+ * Errors: TDGEMM_E_ARG for a NULL plan, TDGEMM_E_HIP if the copy fails. */
+tdgemm_status tdgemm_plan_query(tdgemm_plan_t plan, double *pred_snr_db, int64_t *w_hist,
+                                int64_t *n_short);
+
 /* Copy the plan's statistics and records to host memory. Any pointer may be
  * NULL. Sizes: stats_a nI * nL, stats_b nL * nJ, pairs n_pairs, budgets nI * nJ
  * (D_kernel per inner kernel, SNR mode; 0 otherwise). Synchronises the stream

@@ -1,5 +1,6 @@
 // C-ABI of the tdgemm library: argument validation on the host, workspace
 // layout, plan lifecycle and launches. Declarations and contracts: tdgemm.h.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -13,6 +14,7 @@ struct tdgemm_plan_s {
   tdg::Layout ly;
   char *ws;
   hipStream_t stream;
+  bool tile_map;        // per-inner-kernel targets were given (copied to ws + off_target)
 };
 
 namespace {
@@ -201,6 +203,7 @@ tdgemm_status tdgemm_plan(const tdgemm_desc *desc, const void *A, const void *B,
   tdgemm_plan_s *p = new (std::nothrow) tdgemm_plan_s;
   if (!p) return TDGEMM_E_ARG;
   p->desc = *desc;
+  p->tile_map = desc->tile_target != nullptr;
   p->desc.tile_target = nullptr;          // read here only; not kept
   p->ly = ly;
   p->ws = static_cast<char *>(ws);
@@ -305,6 +308,56 @@ tdgemm_status tdgemm_plan_export(tdgemm_plan_t plan, tdgemm_block_stats *stats_a
     if (hipMemcpy(it.dst, plan->ws + it.off, it.bytes, hipMemcpyDeviceToHost) != hipSuccess)
       return TDGEMM_E_HIP;
   }
+  return TDGEMM_OK;
+}
+
+tdgemm_status tdgemm_plan_query(tdgemm_plan_t plan, double *pred_snr_db, int64_t *w_hist,
+                                int64_t *n_short) {
+  if (!plan) return TDGEMM_E_ARG;
+  if (hipStreamSynchronize(plan->stream) != hipSuccess) return TDGEMM_E_HIP;
+  if (pred_snr_db) *pred_snr_db = INFINITY;
+  if (w_hist)
+    for (int w = 0; w < 5; ++w) w_hist[w] = 0;
+  if (n_short) *n_short = 0;
+  const Layout &ly = plan->ly;
+  const tdgemm_desc &d = plan->desc;
+  if (empty_output(d) || d.K == 0 || ly.n_pairs == 0) return TDGEMM_OK;
+  std::vector<tdgemm_block_stats> sa(ly.nI * ly.nL), sb(ly.nL * ly.nJ);
+  std::vector<tdgemm_pair> pr(ly.n_pairs);
+  const bool target = d.ctrl == TDGEMM_CTRL_TARGET;
+  std::vector<double> tgt(target && plan->tile_map ? ly.nI * ly.nJ : 0);
+  struct Item { void *dst; size_t off, bytes; } items[] = {
+      {sa.data(), ly.off_stats_a, sizeof(tdgemm_block_stats) * sa.size()},
+      {sb.data(), ly.off_stats_b, sizeof(tdgemm_block_stats) * sb.size()},
+      {pr.data(), ly.off_pairs, sizeof(tdgemm_pair) * pr.size()},
+      {tgt.data(), ly.off_target, sizeof(double) * tgt.size()}};
+  for (const Item &it : items) {
+    if (it.bytes == 0) continue;
+    if (hipMemcpy(it.dst, plan->ws + it.off, it.bytes, hipMemcpyDeviceToHost) != hipSuccess)
+      return TDGEMM_E_HIP;
+  }
+  const double tgt_all = std::pow(10.0, 0.1 * d.snr_db);
+  double signal = 0.0, noise = 0.0;
+  int64_t short_pairs = 0;
+  for (int64_t i = 0; i < ly.nI; ++i)
+    for (int64_t j = 0; j < ly.nJ; ++j)
+      for (int64_t l = 0; l < ly.nL; ++l) {
+        const tdgemm_block_stats &a = sa[i * ly.nL + l], &b = sb[l * ly.nJ + j];
+        const tdgemm_pair &o = pr[(i * ly.nJ + j) * ly.nL + l];
+        const double va = a.n > 0 ? a.sumsq / (double)a.n : 0.0;
+        const double vb = b.n > 0 ? b.sumsq / (double)b.n : 0.0;
+        const double l_eff = (double)std::min<int64_t>(d.L, d.K - l * d.L);
+        const double sig = (l_eff * va) * vb;        // expected signal power of the pair
+        signal += sig;
+        noise += o.d;
+        if (w_hist && o.w >= 1 && o.w <= 4) ++w_hist[o.w];
+        if (target && o.w > 1 && o.d > 0.0) {
+          const double want = plan->tile_map ? tgt[i * ly.nJ + j] : tgt_all;
+          if (sig < want * o.d * (1.0 - 1e-9)) ++short_pairs;
+        }
+      }
+  if (pred_snr_db && noise > 0.0) *pred_snr_db = 10.0 * std::log10(signal / noise);
+  if (n_short) *n_short = short_pairs;
   return TDGEMM_OK;
 }
 

@@ -84,6 +84,7 @@ def _load() -> ctypes.CDLL:
         "tdgemm_unpack": (i32, [vp, vp, vp, vp, vp]),
         "tdgemm_plan_export": (i32, [vp, vp, vp, vp, vp]),
         "tdgemm_plan_dims": (i32, [vp, P(i64), P(i64), P(i64), P(i64)]),
+        "tdgemm_plan_query": (i32, [vp, P(dbl), vp, P(i64)]),
         "tdgemm_plan_destroy": (i32, [vp]),
         "tdgemm_calibrate_workspace_size": (sz, [i32, i32]),
         "tdgemm_calibrate": (i32, [i32, i32, i32, i32, vp, i32, vp, vp, i32, dbl, vp, vp, vp,
@@ -280,6 +281,16 @@ def tdgemm_plan_dims(plan: Plan) -> tuple[int, int, int, int]:
     v = [ctypes.c_int64() for _ in range(4)]
     _check(_LIB.tdgemm_plan_dims(plan.handle, *[ctypes.byref(x) for x in v]), "tdgemm_plan_dims")
     return tuple(int(x.value) for x in v)
+
+
+def tdgemm_plan_query(plan: Plan) -> tuple[float, np.ndarray, int]:
+    """(predicted output SNR in dB, W histogram [5], TARGET pairs short of their target)."""
+    snr = ctypes.c_double()
+    hist = np.zeros(5, dtype=np.int64)
+    short = ctypes.c_int64()
+    _check(_LIB.tdgemm_plan_query(plan.handle, ctypes.byref(snr), hist.ctypes.data, ctypes.byref(short)),
+           "tdgemm_plan_query")
+    return float(snr.value), hist, int(short.value)
 
 
 def tdgemm_plan_export(plan: Plan):

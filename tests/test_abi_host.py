@@ -198,3 +198,12 @@ def test_k_split_workspace(binding, lib):
     assert 4 * 256 * 256 * 8 <= extra < 4 * 256 * 256 * 8 + 512
     d8 = _desc(binding, prec=binding.I8, ctrl=binding.CTRL_SEPARABLE, fixed_w=1, L=128, k_split=2)
     assert size(ctypes.byref(d8)) == 0
+
+
+def test_plan_query_rejects_null_plan(lib):
+    f = lib.tdgemm_plan_query
+    f.restype = ctypes.c_int32
+    f.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
+                  ctypes.POINTER(ctypes.c_int64)]
+    snr, short = ctypes.c_double(1.0), ctypes.c_int64(5)
+    assert f(None, ctypes.byref(snr), None, ctypes.byref(short)) == -1

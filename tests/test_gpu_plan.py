@@ -185,3 +185,63 @@ def test_tile_target_plan_parity(td, ctrl, L, form):
     got = C.cpu().numpy()
     assert float(np.linalg.norm(got - Cref) / np.linalg.norm(Cref)) <= 1e-12
     log(f"[plan] tile targets {ctrl}: W histogram {np.bincount(pairs['w'].ravel(), minlength=5).tolist()}")
+
+
+QUERY_CASES = [
+    # name, control, L, form, S (dB), per-tile targets
+    ("snr_L64_sym", "snr", 64, "sym", 30.0, False),
+    ("fixed_L128_asym", "fixed", 128, "asym", 0.0, False),
+    ("target_L96_sym_map", "target", 96, "sym", 40.0, True),
+    ("target_L64_asym_high", "target", 64, "asym", 75.0, False),
+]
+
+
+@pytest.mark.parametrize("case", QUERY_CASES, ids=[c[0] for c in QUERY_CASES])
+def test_plan_query_vs_oracle(td, case):
+    """tdgemm_plan_query against the oracle's own plan: the W histogram exactly,
+    the predicted output SNR (signal L_eff sigma_a^2 sigma_b^2 over D, summed over
+    all pairs) within 1e-9 dB, and the TARGET pairs short of their target."""
+    name, ctrl, L, form, snr, per_tile = case
+    M, K, N = 4 * L - 5, 5 * L + 3, 3 * L + 7
+    nI, nL, nJ = -(-M // L), -(-K // L), -(-N // L)
+    log(f"[plan] query {name}: M={M} K={K} N={N}")
+    A, B = _inputs("laplace", M, K, N, 91 + L)
+    tabs = _calib("std", L, form)
+    wal = (1, 2, _wmax(L))
+    fw = 3 if L == 96 else 2
+    rmax = float(2 ** 14) if L == 96 else float(2 ** 20)
+    tmap = None
+    if per_tile:
+        tmap = np.random.default_rng(5).choice([math.inf, 60.0, 40.0, 20.0], size=(nI, nJ))
+    cfg = pl.Config(L=L, form=form, prec="f64", ctrl=ctrl, snr_db=snr, w_allowed=wal, fixed_w=fw,
+                    fixed_rmax=rmax,
+                    tile_targets=None if tmap is None else tuple(tuple(float(v) for v in r) for r in tmap))
+    ref = pl.make_plan(A, B, cfg, calib=tabs)
+    calib = td.DeviceCalib(tabs[2].r, {W: tabs[W].s for W in (2, _wmax(L))})
+    Ad, Bd = to_dev(A), to_dev(B)
+    desc = td.make_desc(Ad, Bd, L=L, form=form, prec="f64", ctrl=ctrl, snr_db=snr, w_allowed=wal,
+                        fixed_w=fw, fixed_rmax=rmax, tile_target=tmap)
+    plan = td.tdgemm_plan(desc, Ad, Bd, calib if ctrl in ("snr", "target") else None)
+    got_snr, got_hist, got_short = td.tdgemm_plan_query(plan)
+
+    sig, noise, hist, short = [], [], np.zeros(5, dtype=np.int64), 0
+    for i in range(nI):
+        for j in range(nJ):
+            want = 10.0 ** ((tmap[i, j] if tmap is not None else snr) / 10.0)
+            for l in range(nL):
+                o = ref.chosen[(i, j, l)]
+                sa, sb = ref.stats_a[i][l], ref.stats_b[l][j]
+                va = sa.sumsq / sa.n if sa.n else 0.0
+                vb = sb.sumsq / sb.n if sb.n else 0.0
+                s = min(L, K - l * L) * va * vb
+                sig.append(s)
+                noise.append(o.d)
+                hist[o.W] += 1
+                if ctrl == "target" and o.W > 1 and o.d > 0.0 and s < want * o.d * (1.0 - 1e-9):
+                    short += 1
+    assert got_hist.tolist() == hist.tolist()
+    assert got_short == short
+    n_sum = math.fsum(noise)
+    want_snr = math.inf if n_sum == 0.0 else 10.0 * math.log10(math.fsum(sig) / n_sum)
+    assert (got_snr == want_snr) if math.isinf(want_snr) else abs(got_snr - want_snr) <= 1e-9
+    log(f"[plan] query {name}: predicted SNR {got_snr:.3f} dB, W {got_hist.tolist()}, short {got_short}")
