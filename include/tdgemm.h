@@ -226,7 +226,10 @@ tdgemm_status tdgemm_unpack(tdgemm_plan_t plan, const void *Rbar, void *r_int, v
  *               pairs of the signal power L_eff sigma_a^2 sigma_b^2 (block RMS
  *               values, L_eff the valid inner extent) over the sum of their
  *               expected noise powers D (eq. 21); +inf when every D is 0 (all
- *               native, or an empty product).
+ *               native, or an empty product). Block-scaled forms: D is the noise
+ *               of rounding to the integer grid of range sep_q (eq. 19), which
+ *               fits INT8; E4M3 rounds more coarsely (3 mantissa bits), so its
+ *               prediction is optimistic.
  *  w_hist       5 counters: w_hist[W] = pairs at packing W (W = 1..4); w_hist[0] = 0.
  *  n_short      TARGET control: pairs at W >= 2 whose expected SNR (signal / D)
  *               is below their target (eq. 25 fails there and the eq. (26)

@@ -135,3 +135,29 @@ def test_block_scaled_rejects_bad_descriptors(td):
         with pytest.raises(td.TdgemmError) as e:
             td.tdgemm_plan(desc, A, A, None)
         assert status in str(e.value)
+
+
+@pytest.mark.parametrize("fmt,q", [("i8", 127.0), ("e4m3", 448.0)])
+def test_block_scaled_plan_query(td, fmt, q):
+    """tdgemm_plan_query on the block-scaled form: every pair W = 1, and the
+    predicted SNR from the oracle's records (signal L_eff sigma_a^2 sigma_b^2 over D)."""
+    M, K, N = 300, 400, 260
+    A, B = _inputs(M, K, N, np.float64, 17)
+    ref = pr.run(A, B, 128, fmt, q, keep_products=False)
+    Ad, Bd = to_dev(A), to_dev(B)
+    desc = td.make_desc(Ad, Bd, L=128, prec=fmt, ctrl="separable", fixed_w=1, sep_q=q)
+    plan = td.tdgemm_plan(desc, Ad, Bd, None)
+    got_snr, hist, short = td.tdgemm_plan_query(plan)
+    nI, nL, nJ, npairs = plan.dims
+    assert hist.tolist() == [0, npairs, 0, 0, 0] and short == 0
+    sig, noise = [], []
+    for (i, j, l), o in ref.options.items():
+        sa, sb = ref.stats_a[i][l], ref.stats_b[l][j]
+        va = sa.sumsq / sa.n if sa.n else 0.0
+        vb = sb.sumsq / sb.n if sb.n else 0.0
+        sig.append(min(128, K - l * 128) * va * vb)
+        noise.append(o.d)
+    n_sum = math.fsum(noise)
+    want = math.inf if n_sum == 0.0 else 10.0 * math.log10(math.fsum(sig) / n_sum)
+    assert (got_snr == want) if math.isinf(want) else abs(got_snr - want) <= 1e-9
+    log(f"[precision] plan query {fmt}: predicted SNR {got_snr:.2f} dB")
