@@ -54,6 +54,12 @@ CASES = [
     ("f32_in_f64_pack", 200, 300, 100, 64, "sym", "f32", "f64", "snr", 40.0, (1, 2), 2, 0, 0),
     ("f32_pack_sym", 200, 300, 100, 64, "sym", "f32", "f32", "snr", 15.0, (1, 2), 2, 0, 0),
     ("f32_pack_asym_L128", 200, 300, 160, 128, "asym", "f32", "f32", "snr", 10.0, (1, 2), 2, 0, 0),
+    # the instantiations the scatter (FP32 in, FP64 packing, A transposed) and the
+    # perceptron (FP32 packing, either operand transposed) workloads run at L = 128
+    ("L128_f32_in_f64_ta", 300, 260, 280, 128, "sym", "f32", "f64", "snr", 40.0, (1, 2, 4), 2, 1, 0),
+    ("L128_f32_in_f64_asym", 200, 300, 150, 128, "asym", "f32", "f64", "snr", 30.0, (1, 2, 4), 2, 0, 0),
+    ("L128_f32_pack_sym_ta", 260, 300, 140, 128, "sym", "f32", "f32", "snr", 15.0, (1, 2), 2, 1, 0),
+    ("L128_f32_pack_sym_tb", 200, 300, 160, 128, "sym", "f32", "f32", "snr", 15.0, (1, 2), 2, 0, 1),
     ("separable_q127", 256, 256, 192, 128, "sym", "f64", "f64", "separable", 0.0, (1, 2), 2, 0, 0),
     ("single_row", 1, 100, 70, 64, "sym", "f64", "f64", "snr", 40.0, (1, 2), 2, 0, 0),
     ("k_below_L", 70, 20, 90, 64, "asym", "f64", "f64", "snr", 30.0, (1, 2, 4), 2, 0, 0),
