@@ -12,7 +12,8 @@ Readings taken:
   R_max range. The range needed here is far wider, and the eq. (26) companders
   make Q_A / Q_B = (max|A|/s_a) / (max|B|/s_b), about 1 for i.i.d. blocks, so
   the sweep uses max|A| = max|B| = q over a geometric grid of integers q,
-  giving R_max = L q^2.
+  giving R_max = L q^2. ``measure`` also takes a separate max|B| (R_max =
+  L max|A| max|B|), the paper's own protocol.
 * Eq. (18) prints (1/L^2) times a Frobenius norm; s is read as the per-output
   RMSE sqrt(mean e^2) and m as the mean error, in integer (index) units, over
   all outputs of all instances. Both sums are exactly rounded.
@@ -52,14 +53,18 @@ def q_grid(q_max: int = 1 << 20, steps_per_octave: int = 8) -> list[int]:
 
 
 def measure(L: int, W: int, form: str, prec: str, q: int, u_a: np.ndarray, u_b: np.ndarray,
-            u_safe: float = 50.0) -> tuple[float, float, float]:
-    """(R_max, m, s) of the packed product at range q, over all instances."""
-    r_max = float(L) * float(q) * float(q)
+            u_safe: float = 50.0, q_b: int | None = None) -> tuple[float, float, float]:
+    """(R_max, m, s) of eq. (18) for the packed product with max|A| = q and
+    max|B| = q_b (default q), over all instances: R_max = L q q_b (eq. 17 with
+    c = 1), m the mean and s the root mean square of the unpacked-minus-exact
+    errors over every output of every instance."""
+    q_b = q if q_b is None else q_b
+    r_max = float(L) * float(q) * float(q_b)
     p = pk.packing_exponent(r_max, u_safe)
     errs = []
     for t in range(u_a.shape[0]):
         a = int_inputs(u_a[t], q)
-        b = int_inputs(u_b[t], q)
+        b = int_inputs(u_b[t], q_b)
         exact = a.astype(np.int64) @ b.astype(np.int64)
         dt = pk.DTYPES[prec]
         qa, qb = a.astype(dt), b.astype(dt)

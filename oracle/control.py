@@ -22,8 +22,10 @@ Readings taken:
   pair contribute nothing: c = 0, inverse 0, D = 0, at the maximum W.
 * Pruning: "removing the outcome with the highest distortion" lowers that
   pair to the next smaller allowed W (ties: lowest l). Both sums of Sec. 6 are
-  exactly rounded. An option a table cannot supply has D = 1e300, so it is
-  removed first.
+  exactly rounded. An option a table cannot supply (no finite s(R, W), or no
+  grid point where the eq. 27 noise is finite) has D = 1e300: it is removed
+  first, and it is always removed, whatever the budget or the throughput
+  target, because its subblock product could not be formed.
 * Border pairs use L_eff, the valid inner extent, wherever L appears.
 """
 from __future__ import annotations
@@ -104,14 +106,20 @@ def best_option(W: int, L_eff: int, sa: BlockStats, sb: BlockStats, table: Calib
     r = table.r[ok]
     s = table.s[ok]
     s_a, s_b = sa.sigma, sb.sigma
+    unavailable = PairOption(W, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, option_zero(W, u_safe).p, 0.0,
+                             D_UNAVAILABLE, np.inf, np.inf)
     # eq. (27) noise at every grid R, elementwise in the same operation order as nsr_prop4
-    ctot = ((float(L_eff) * sa.amax) * sb.amax) / r
-    ss = s_a * s_b
-    t1 = ctot / (6.0 * ss)
-    t2 = (ctot * ctot) / (144.0 * (ss * ss))
-    t3 = ((s * s) * (ctot * ctot)) / (float(L_eff) * (ss * ss))
-    nsr = (t1 + t2) + t3
-    k = int(np.argmin(nsr))           # first minimum: the smaller R on ties
+    with np.errstate(over="ignore", invalid="ignore"):
+        ctot = ((float(L_eff) * sa.amax) * sb.amax) / r
+        ss = s_a * s_b
+        t1 = ctot / (6.0 * ss)
+        t2 = (ctot * ctot) / (144.0 * (ss * ss))
+        t3 = ((s * s) * (ctot * ctot)) / (float(L_eff) * (ss * ss))
+        nsr = (t1 + t2) + t3
+    fin = np.isfinite(nsr)            # an overflowed (inf or nan) noise is no candidate
+    if not fin.any():
+        return unavailable
+    k = int(np.flatnonzero(fin)[np.argmin(nsr[fin])])   # first minimum: the smaller R on ties
     return option_at(W, L_eff, sa, sb, float(r[k]), float(s[k]), u_safe)
 
 
@@ -197,6 +205,8 @@ def prune_accel(options: list[dict[int, PairOption]], w_desc: list[int], frac: f
     the drop; it stops before the first drop that would break the constraint
     and once the highest remaining distortion is 0 (nothing to gain). With
     W in {1, 2}, frac is the fraction of subblock products that stay packed.
+    An unavailable option (D >= D_UNAVAILABLE) drops whatever the constraint:
+    its product could not be formed.
     """
     nl = len(options)
     level = [0] * nl
@@ -215,7 +225,7 @@ def prune_accel(options: list[dict[int, PairOption]], w_desc: list[int], frac: f
             break
         w_now, w_next = w_desc[level[lstar]], w_desc[level[lstar] + 1]
         after = saved - saved_units(w_now) + saved_units(w_next)
-        if after < target:
+        if after < target and d[lstar] < D_UNAVAILABLE:
             break
         saved = after
         level[lstar] += 1
@@ -239,11 +249,13 @@ def prune(options: list[dict[int, PairOption]], w_desc: list[int], d_kernel: flo
 
     options[l][W] is the pair option of subblock l at packing W; w_desc lists
     the allowed packings in descending order. Returns the chosen W per l.
+    Removal goes on while the sum exceeds the budget or an unavailable option
+    (D >= D_UNAVAILABLE, always the largest) is still current.
     """
     nl = len(options)
     level = [0] * nl
     d = [options[l][w_desc[0]].d for l in range(nl)]
-    while exact_sum(d) > d_kernel:
+    while True:
         cand = [l for l in range(nl) if level[l] < len(w_desc) - 1]
         if not cand:
             break
@@ -251,6 +263,8 @@ def prune(options: list[dict[int, PairOption]], w_desc: list[int], d_kernel: flo
         for l in cand[1:]:
             if d[l] > d[lstar]:
                 lstar = l
+        if not exact_sum(d) > d_kernel and d[lstar] < D_UNAVAILABLE:
+            break
         level[lstar] += 1
         d[lstar] = options[lstar][w_desc[level[lstar]]].d
     return [w_desc[level[l]] for l in range(nl)]

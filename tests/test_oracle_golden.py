@@ -1,12 +1,9 @@
 """Pins of the oracle against values the paper prints (fixtures in tests/golden/)."""
-import math
 import pathlib
 
 import numpy as np
 
-from oracle import packing as pk
-from oracle.calibration import int_inputs
-from oracle.exactsum import exact_sum
+from oracle.calibration import measure
 
 GOLDEN = pathlib.Path(__file__).parent / "golden"
 
@@ -30,22 +27,11 @@ def test_sec4b_single_precision_symmetric_w2_error_bounds():
     f = _fixture("sec4b_sp_sym_w2_bounds.txt")
     L, W = int(f["L"]), int(f["W"])
     qa, qb = int(f["max_a"]), int(f["max_b"])
-    r_max = float(L * qa * qb)
-    assert r_max <= 320000.0
-    p = pk.packing_exponent(r_max, 50.0)
+    inst = int(f["instances"])
     rng = np.random.default_rng(20111)
-    errs = []
-    for _ in range(int(f["instances"])):
-        a = int_inputs(rng.random((L, L)), qa)
-        b = int_inputs(rng.random((L, L)), qb)
-        exact = a.astype(np.int64) @ b.astype(np.int64)
-        abar = pk.pack_sym_a(a.astype(np.float32), W, p, "f32")
-        bbar = pk.pack_sym_b(b.astype(np.float32), W, p, "f32")
-        r = pk.unpack_sym(pk.packed_product(abar, bbar, "f32"), p, "f32")
-        errs.append((np.asarray(r, dtype=np.float64) - exact).ravel())
-    e = np.concatenate(errs)
-    m = exact_sum(e.tolist()) / e.size
-    s = math.sqrt(exact_sum((e * e).tolist()) / e.size)
+    ua, ub = rng.random((inst, L, L)), rng.random((inst, L, L))
+    r_max, m, s = measure(L, W, f["form"], f["prec"], qa, ua, ub, q_b=qb)
+    assert r_max == float(L * qa * qb) and r_max <= 320000.0
     k = float(f["magnitude_factor"])
     assert s / r_max < k * float(f["s_over_rmax_below"]), (s, r_max)
     assert s / r_max > float(f["s_over_rmax_below"]) / k, (s, r_max)
