@@ -48,13 +48,26 @@ def _compile(src: pathlib.Path) -> pathlib.Path:
     return obj
 
 
-def build(jobs: int | None = None) -> pathlib.Path:
-    """Compile every source and link the shared library; returns its path."""
+def _fresh(src: pathlib.Path, headers: list[pathlib.Path]) -> bool:
+    """True when src's object is newer than src and every header."""
+    obj = BUILD / (src.stem + ".o")
+    if not obj.exists():
+        return False
+    t = obj.stat().st_mtime
+    return all(p.stat().st_mtime < t for p in [src, *headers])
+
+
+def build(jobs: int | None = None, incremental: bool = False) -> pathlib.Path:
+    """Compile every source and link the shared library; returns its path.
+    incremental: reuse objects newer than their source and every header."""
     BUILD.mkdir(exist_ok=True)
     srcs = sorted(CSRC.glob("*.hip")) + sorted(CSRC.glob("*.cpp"))
-    jobs = jobs or min(8, len(srcs))
+    headers = sorted(CSRC.glob("*.h")) + sorted((ROOT / "include").glob("*.h"))
+    todo = [s for s in srcs if not (incremental and _fresh(s, headers))]
+    jobs = jobs or min(8, max(1, len(todo)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        list(ex.map(_compile, todo))
+    objs = [BUILD / (s.stem + ".o") for s in srcs]
     tmp = LIB.with_suffix(".so.tmp")
     cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", str(tmp),
            *[str(o) for o in objs]]
@@ -66,4 +79,4 @@ def build(jobs: int | None = None) -> pathlib.Path:
 
 
 if __name__ == "__main__":
-    print(build())
+    print(build(incremental="--incremental" in sys.argv))

@@ -6,23 +6,17 @@
 #include <new>
 #include <vector>
 
-#include "common.h"
-#include "kernels.h"
-
-struct tdgemm_plan_s {
-  tdgemm_desc desc;
-  tdg::Layout ly;
-  char *ws;
-  hipStream_t stream;
-  bool tile_map;        // per-inner-kernel targets were given (copied to ws + off_target)
-};
+#include "api_internal.h"
 
 namespace {
 
 using tdg::Layout;
 using tdg::Problem;
+using tdg::layout_of;
 
 bool is_finite(double x) { return std::isfinite(x); }
+
+constexpr int64_t kMaxTileSpan = int64_t(1) << 31;   // L * lda and L * ldb must stay below
 
 bool valid_l(int L) { return L == 64 || L == 96 || L == 128; }
 
@@ -38,7 +32,13 @@ tdgemm_status check_w(int w, int L) {
 
 bool block_scaled(int prec) { return prec == TDGEMM_I8 || prec == TDGEMM_E4M3; }
 
-tdgemm_status validate(const tdgemm_desc *d) {
+}  // namespace
+
+namespace tdg {
+
+bool is_block_scaled(int prec) { return block_scaled(prec); }
+
+tdgemm_status validate_desc(const tdgemm_desc *d) {
   if (!d) return TDGEMM_E_ARG;
   if (d->M < 0 || d->N < 0 || d->K < 0) return TDGEMM_E_ARG;
   if (d->trans_a != 0 && d->trans_a != 1) return TDGEMM_E_ARG;
@@ -61,6 +61,9 @@ tdgemm_status validate(const tdgemm_desc *d) {
   if (d->lda < (need_a > 0 ? need_a : 1) || d->ldb < (need_b > 0 ? need_b : 1) ||
       d->ldc < (d->N > 0 ? d->N : 1))
     return TDGEMM_E_ARG;
+  // the fused kernel addresses an element of a tile by a 32-bit offset below L * ld
+  if ((int64_t)d->L * d->lda >= kMaxTileSpan || (int64_t)d->L * d->ldb >= kMaxTileSpan)
+    return TDGEMM_E_UNSUPPORTED;
   if (!(d->u_safe > 0.0) || !is_finite(d->u_safe)) return TDGEMM_E_ARG;
   switch (d->ctrl) {
     case TDGEMM_CTRL_ACCEL:
@@ -121,6 +124,12 @@ Layout layout_of(const tdgemm_desc &d) {
   return tdg::make_layout(d.M, d.N, d.K, d.L, d.k_split, elem);
 }
 
+}  // namespace tdg
+
+namespace {
+
+tdgemm_status validate(const tdgemm_desc *d) { return tdg::validate_desc(d); }
+
 Problem problem_of(const tdgemm_desc &d, const Layout &ly) {
   Problem p;
   p.M = d.M; p.N = d.N; p.K = d.K;
@@ -165,6 +174,91 @@ int packing_exponent_host(double r_safe, double u_safe) {
 
 }  // namespace
 
+namespace tdg {
+
+tdgemm_status check_plan_inputs(const tdgemm_desc &d, const void *A, const void *B,
+                                const tdgemm_calib *calib) {
+  if (!empty_output(d) && d.K > 0 && (!A || !B)) return TDGEMM_E_ARG;
+  const bool tables = d.ctrl == TDGEMM_CTRL_SNR || d.ctrl == TDGEMM_CTRL_ACCEL ||
+                      d.ctrl == TDGEMM_CTRL_TARGET;
+  if (tables && (!calib || calib->n_r < 1 || calib->n_r > 512 || !calib->r || !calib->s))
+    return TDGEMM_E_CALIB;
+  return TDGEMM_OK;
+}
+
+hipError_t enqueue_plan(const tdgemm_plan_s &p, const void *A, const void *B,
+                        const tdgemm_calib *calib, const double *tile_target) {
+  const tdgemm_desc &d = p.desc;
+  const Layout &ly = p.ly;
+  if (empty_output(d) || d.K == 0) return hipSuccess;      // no pairs
+  const bool with_options = d.ctrl == TDGEMM_CTRL_SNR || d.ctrl == TDGEMM_CTRL_ACCEL;
+  auto *sa = reinterpret_cast<tdgemm_block_stats *>(p.ws + ly.off_stats_a);
+  auto *sb = reinterpret_cast<tdgemm_block_stats *>(p.ws + ly.off_stats_b);
+  auto *tab = reinterpret_cast<PlanTable *>(p.ws + ly.off_table);
+  StatsArgs sargs;
+  sargs.A = A; sargs.B = B;
+  sargs.M = d.M; sargs.N = d.N; sargs.K = d.K;
+  sargs.lda = d.lda; sargs.ldb = d.ldb;
+  sargs.ta = d.trans_a != 0; sargs.tb = d.trans_b != 0;
+  sargs.nI = ly.nI; sargs.nL = ly.nL; sargs.nJ = ly.nJ;
+  sargs.stats_a = sa; sargs.stats_b = sb;
+  sargs.calib_r = with_options ? calib->r : nullptr;
+  sargs.calib_s = with_options ? calib->s : nullptr;
+  sargs.n_r = with_options ? calib->n_r : 0;
+  sargs.table = with_options ? tab : nullptr;
+  hipError_t e = launch_stats(sargs, d.in_dtype, d.L, p.stream);
+  if (e != hipSuccess) return e;
+  PlanLaunch pl;
+  pl.pb = problem_of(d, ly);
+  pl.stats_a = sa;
+  pl.stats_b = sb;
+  pl.pairs = reinterpret_cast<tdgemm_pair *>(p.ws + ly.off_pairs);
+  pl.budget = reinterpret_cast<double *>(p.ws + ly.off_budget);
+  pl.calib_r = calib ? calib->r : nullptr;
+  pl.calib_s = calib ? calib->s : nullptr;
+  pl.table = tab;
+  pl.n_r = calib ? calib->n_r : 0;
+  pl.ctrl = d.ctrl;
+  pl.n_opt = 0;
+  for (int w : {4, 3, 2, 1})
+    if (!with_options || (d.w_allowed & (1u << w))) pl.w_desc[pl.n_opt++] = w;
+  if (!with_options) { pl.n_opt = 1; pl.w_desc[0] = d.fixed_w; }
+  pl.accel = d.accel;
+  pl.fixed_w = d.fixed_w;
+  pl.block_scaled = block_scaled(d.prec) ? 1 : 0;
+  pl.fixed_rmax = d.fixed_rmax;
+  pl.sep_q = d.sep_q;
+  pl.u_safe = d.u_safe;
+  pl.snr_lin = std::pow(10.0, -d.snr_db / 10.0);
+  pl.tgt_pow = std::pow(10.0, 0.1 * d.snr_db);
+  pl.tile = nullptr;
+  if (tile_target) {
+    // per inner kernel: 10^(-S/10) (SNR), 10^(S/10) (TARGET) or F_kernel (ACCEL),
+    // copied next to the plan
+    const int64_t nt = ly.nI * ly.nJ;
+    std::vector<double> h(nt);
+    for (int64_t t = 0; t < nt; ++t)
+      h[t] = d.ctrl == TDGEMM_CTRL_SNR    ? std::pow(10.0, -tile_target[t] / 10.0)
+           : d.ctrl == TDGEMM_CTRL_TARGET ? std::pow(10.0, 0.1 * tile_target[t])
+                                          : tile_target[t];
+    double *dt = reinterpret_cast<double *>(p.ws + ly.off_target);
+    e = hipMemcpyAsync(dt, h.data(), sizeof(double) * nt, hipMemcpyHostToDevice, p.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p.stream);   // h is released below
+    if (e != hipSuccess) return e;
+    pl.tile = dt;
+  }
+  return launch_plan(pl, p.stream);
+}
+
+hipError_t enqueue_fused(const tdgemm_plan_s &p, const void *A, const void *B, void *C) {
+  const tdgemm_desc &d = p.desc;
+  if (empty_output(d)) return hipSuccess;
+  if (d.K == 0) return launch_fill_zero(C, d.prec, d.M, d.N, d.ldc, p.stream);
+  return launch_fused(operands_of(&p), A, B, C, p.ws + p.ly.off_part, p.stream);
+}
+
+}  // namespace tdg
+
 extern "C" {
 
 const char *tdgemm_status_string(tdgemm_status s) {
@@ -192,14 +286,10 @@ tdgemm_status tdgemm_plan(const tdgemm_desc *desc, const void *A, const void *B,
   tdgemm_status s = validate(desc);
   if (s != TDGEMM_OK) return s;
   const Layout ly = layout_of(*desc);
-  const bool has_work = !empty_output(*desc) && desc->K > 0;
-  if (has_work && (!A || !B)) return TDGEMM_E_ARG;
+  if (!empty_output(*desc) && desc->K > 0 && (!A || !B)) return TDGEMM_E_ARG;
   if (!ws || ws_bytes < ly.total) return TDGEMM_E_WORKSPACE;
-  const bool with_options = desc->ctrl == TDGEMM_CTRL_SNR || desc->ctrl == TDGEMM_CTRL_ACCEL;
-  if (with_options || desc->ctrl == TDGEMM_CTRL_TARGET) {
-    if (!calib || calib->n_r < 1 || calib->n_r > 512 || !calib->r || !calib->s)
-      return TDGEMM_E_CALIB;
-  }
+  s = tdg::check_plan_inputs(*desc, A, B, calib);
+  if (s != TDGEMM_OK) return s;
   tdgemm_plan_s *p = new (std::nothrow) tdgemm_plan_s;
   if (!p) return TDGEMM_E_ARG;
   p->desc = *desc;
@@ -208,67 +298,9 @@ tdgemm_status tdgemm_plan(const tdgemm_desc *desc, const void *A, const void *B,
   p->ly = ly;
   p->ws = static_cast<char *>(ws);
   p->stream = static_cast<hipStream_t>(stream);
-  if (has_work) {
-    auto *sa = reinterpret_cast<tdgemm_block_stats *>(p->ws + ly.off_stats_a);
-    auto *sb = reinterpret_cast<tdgemm_block_stats *>(p->ws + ly.off_stats_b);
-    auto *tab = reinterpret_cast<tdg::PlanTable *>(p->ws + ly.off_table);
-    const bool snr = with_options;
-    tdg::StatsArgs sargs;
-    sargs.A = A; sargs.B = B;
-    sargs.M = desc->M; sargs.N = desc->N; sargs.K = desc->K;
-    sargs.lda = desc->lda; sargs.ldb = desc->ldb;
-    sargs.ta = desc->trans_a != 0; sargs.tb = desc->trans_b != 0;
-    sargs.nI = ly.nI; sargs.nL = ly.nL; sargs.nJ = ly.nJ;
-    sargs.stats_a = sa; sargs.stats_b = sb;
-    sargs.calib_r = snr ? calib->r : nullptr;
-    sargs.calib_s = snr ? calib->s : nullptr;
-    sargs.n_r = snr ? calib->n_r : 0;
-    sargs.table = snr ? tab : nullptr;
-    hipError_t e = tdg::launch_stats(sargs, desc->in_dtype, desc->L, p->stream);
-    if (e == hipSuccess) {
-      tdg::PlanLaunch pl;
-      pl.pb = problem_of(*desc, ly);
-      pl.stats_a = sa;
-      pl.stats_b = sb;
-      pl.pairs = reinterpret_cast<tdgemm_pair *>(p->ws + ly.off_pairs);
-      pl.budget = reinterpret_cast<double *>(p->ws + ly.off_budget);
-      pl.calib_r = calib ? calib->r : nullptr;
-      pl.calib_s = calib ? calib->s : nullptr;
-      pl.table = tab;
-      pl.n_r = calib ? calib->n_r : 0;
-      pl.ctrl = desc->ctrl;
-      pl.n_opt = 0;
-      for (int w : {4, 3, 2, 1})
-        if (!with_options || (desc->w_allowed & (1u << w))) pl.w_desc[pl.n_opt++] = w;
-      if (!with_options) { pl.n_opt = 1; pl.w_desc[0] = desc->fixed_w; }
-      pl.accel = desc->accel;
-      pl.fixed_w = desc->fixed_w;
-      pl.block_scaled = block_scaled(desc->prec) ? 1 : 0;
-      pl.fixed_rmax = desc->fixed_rmax;
-      pl.sep_q = desc->sep_q;
-      pl.u_safe = desc->u_safe;
-      pl.snr_lin = std::pow(10.0, -desc->snr_db / 10.0);
-      pl.tgt_pow = std::pow(10.0, 0.1 * desc->snr_db);
-      pl.tile = nullptr;
-      if (desc->tile_target) {
-        // per inner kernel: 10^(-S/10) (SNR) or F_kernel (ACCEL), copied next to the plan
-        const int64_t nt = ly.nI * ly.nJ;
-        std::vector<double> h(nt);
-        for (int64_t t = 0; t < nt; ++t)
-          h[t] = desc->ctrl == TDGEMM_CTRL_SNR    ? std::pow(10.0, -desc->tile_target[t] / 10.0)
-               : desc->ctrl == TDGEMM_CTRL_TARGET ? std::pow(10.0, 0.1 * desc->tile_target[t])
-                                                  : desc->tile_target[t];
-        double *dt = reinterpret_cast<double *>(p->ws + ly.off_target);
-        e = hipMemcpyAsync(dt, h.data(), sizeof(double) * nt, hipMemcpyHostToDevice, p->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);   // h is released below
-        pl.tile = dt;
-      }
-      if (e == hipSuccess) e = tdg::launch_plan(pl, p->stream);
-    }
-    if (e != hipSuccess) {
-      delete p;
-      return TDGEMM_E_HIP;
-    }
+  if (tdg::enqueue_plan(*p, A, B, calib, desc->tile_target) != hipSuccess) {
+    delete p;
+    return TDGEMM_E_HIP;
   }
   *out = p;
   return TDGEMM_OK;

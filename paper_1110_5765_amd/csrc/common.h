@@ -31,7 +31,8 @@ __device__ __forceinline__ void lds_barrier() {
 // Compensated sums. A running sum is a pair (s, c): s the rounded sum, c the
 // accumulated rounding errors (each obtained exactly by TwoSum). s + c rounded
 // once is the exactly rounded sum except when the exact value lies within about
-// n^2 2^-106 |sum| of a rounding boundary.
+// n^2 2^-106 |sum| of a rounding boundary; certified_round() below detects that
+// case and the callers then sum exactly.
 struct CSum {
   double s, c;
 };
@@ -56,15 +57,115 @@ __device__ __forceinline__ CSum csum_merge(CSum x, CSum y) {
 
 __device__ __forceinline__ double csum_value(CSum x) { return x.s + x.c; }
 
-// Butterfly merge over the 64 lanes, then lane 0's value broadcast so every
-// lane holds the same rounded result.
-__device__ __forceinline__ double wave_csum(CSum x) {
+// Butterfly merge over the 64 lanes, then lane 0's pair broadcast so every lane
+// holds the same (s, c).
+__device__ __forceinline__ CSum wave_csum_pair(CSum x) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     CSum y{__shfl_xor(x.s, off), __shfl_xor(x.c, off)};
     x = csum_merge(x, y);
   }
-  return __shfl(csum_value(x), 0);
+  return CSum{__shfl(x.s, 0), __shfl(x.c, 0)};
+}
+
+// ---------------------------------------------------------------------------
+// Exactly rounded sums by construction. A compensated pair (s, c) of n terms
+// whose exact sum S is at least as large as the sum of their magnitudes up to
+// a factor 1 + 2^-50 (non-negative terms, or squares split exactly into a
+// rounded square and its error) satisfies |S - (s + c)| <= ~(n 2^-53)^2 |S|.
+// exact_bound() is n^2 2^-100 |s + c|, a generous multiple of that.
+// certified_round() returns r = fl(s + c) and whether r is certainly the
+// exactly rounded S: S then lies strictly inside r's rounding interval. Where
+// it does not, the caller sums the terms again with the partials method of
+// Shewchuk (Adaptive Precision Floating-Point Arithmetic, 1997): exact
+// non-overlapping partials, then one rounding to nearest, ties to even.
+__device__ __forceinline__ double exact_bound(int64_t n, double r) {
+  return (((double)n * (double)n) * 0x1p-100) * fabs(r);
+}
+
+__device__ __forceinline__ bool certified_round(double s, double c, int64_t n, double &r) {
+  double t;
+  two_sum(s, c, r, t);                            // r + t = s + c exactly
+  if (r == 0.0 || !isfinite(r)) return true;      // all terms zero, or overflow either way
+  const double ar = fabs(r);
+  const int64_t bits = __double_as_longlong(ar);
+  // distance from r to its neighbour on the side of t
+  const bool away = (t >= 0.0) == (r > 0.0);
+  const double gap = away ? __longlong_as_double(bits + 1) - ar : ar - __longlong_as_double(bits - 1);
+  return fabs(t) + exact_bound(n, r) < 0.5 * gap;
+}
+
+// Exact partials: part[0..np) non-overlapping, increasing in magnitude, summing
+// exactly to every term added so far. At most 64 partials are ever needed for
+// binary64 (each covers a disjoint range of the 2098 exponent bits).
+constexpr int kMaxPartials = 64;
+
+__device__ __forceinline__ void partials_add(double *part, int &np, double x) {
+  int k = 0;
+  for (int j = 0; j < np; ++j) {
+    double y = part[j];
+    if (fabs(x) < fabs(y)) { const double tmp = x; x = y; y = tmp; }
+    const double hi = x + y;                      // |x| >= |y|: hi + lo == x + y exactly
+    const double lo = y - (hi - x);
+    if (lo != 0.0) part[k++] = lo;
+    x = hi;
+  }
+  np = k;
+  if (x != 0.0) part[np++] = x;
+}
+
+// The sum of the partials rounded once to nearest (ties to even).
+__device__ __forceinline__ double partials_round(const double *part, int np) {
+  if (np == 0) return 0.0;
+  int n = np - 1;
+  double hi = part[n], lo = 0.0;
+  while (n > 0) {                                 // add from the top while exact
+    const double x = hi, y = part[--n];
+    hi = x + y;
+    lo = y - (hi - x);
+    if (lo != 0.0) break;
+  }
+  // hi + lo is exact but the partials below lo may push the sum past the
+  // half-way point that hi's rounding assumed: then round the other way
+  if (n > 0 && ((lo < 0.0 && part[n - 1] < 0.0) || (lo > 0.0 && part[n - 1] > 0.0))) {
+    const double y = lo * 2.0;
+    const double x = hi + y;
+    if (x - hi == y) hi = x;
+  }
+  return hi;
+}
+
+// Exactly rounded sum of v[0..TT) over the 64 lanes of a wavefront; every lane
+// gets the same value. scr: this wavefront's LDS scratch of at least 64 TT + 64
+// doubles, used only when the compensated sum cannot be certified.
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int TT>
+__device__ __forceinline__ double wave_sum_exact(const double (&v)[TT], double *scr) {
+  const int lane = threadIdx.x & (kWave - 1);
+  CSum x{0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < TT; ++t) x = csum_add(x, v[t]);
+  x = wave_csum_pair(x);
+  double r;
+  if (certified_round(x.s, x.c, (int64_t)kWave * TT, r)) return r;
+  wave_sync_lds();
+#pragma unroll
+  for (int t = 0; t < TT; ++t) scr[t * kWave + lane] = v[t];
+  wave_sync_lds();
+  if (lane == 0) {
+    double *part = scr + kWave * TT;
+    int np = 0;
+    for (int k = 0; k < kWave * TT; ++k) partials_add(part, np, scr[k]);
+    r = partials_round(part, np);
+  }
+  r = __shfl(r, 0);
+  wave_sync_lds();
+  return r;
 }
 
 // ---------------------------------------------------------------------------

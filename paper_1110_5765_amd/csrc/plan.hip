@@ -8,8 +8,8 @@ namespace tdg {
 // ---------------------------------------------------------------------------
 // Block statistics. The result of a block does not depend on the order in
 // which its elements are visited (min and max are exact, the sum of squares is
-// compensated and rounded once), so every block is read in its stored layout:
-// a transposed operand is the same set of elements.
+// exactly rounded), so every block is read in its stored layout: a transposed
+// operand is the same set of elements.
 
 struct StatAcc {
   double mn, mx;
@@ -70,15 +70,51 @@ __device__ __forceinline__ void block_stats(const T *__restrict__ X, int64_t ld,
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc = stat_merge(acc, stat_shfl_xor(acc, off));
   __shared__ StatAcc s_w[kThreads / kWave];
+  __shared__ double s_sum;
+  __shared__ int s_certified;
   if ((tid & (kWave - 1)) == 0) s_w[tid / kWave] = acc;
   __syncthreads();
   if (tid == 0) {
     StatAcc t = s_w[0];
     for (int q = 1; q < kThreads / kWave; ++q) t = stat_merge(t, s_w[q]);
+    double r;
+    // 2 terms (rounded square and its error) per valid element
+    s_certified = certified_round(t.s.s, t.s.c, 2 * (int64_t)vr * vc, r) ? 1 : 0;
+    s_sum = r;
+    s_w[0] = t;
+  }
+  __syncthreads();
+  if (!s_certified) {
+    // The sum lies too close to a rounding boundary for the compensated pair to
+    // decide: thread 0 adds every square, split exactly into its rounded value
+    // and error, into exact partials, the workgroup staging the terms in LDS.
+    __shared__ double s_terms[2 * kThreads];
+    __shared__ double s_part[kMaxPartials];
+    int np = 0;
+    for (int e0 = 0; e0 < L * L; e0 += kThreads) {
+      const int e = e0 + tid;
+      const int r = e / L, c = e - (e / L) * L;
+      double p = 0.0, pe = 0.0;
+      if (r < vr && c < vc) {
+        const double x = (double)X[(int64_t)r * ld + c];
+        p = x * x;
+        pe = __builtin_fma(x, x, -p);
+      }
+      s_terms[2 * tid] = p;
+      s_terms[2 * tid + 1] = pe;
+      __syncthreads();
+      if (tid == 0)
+        for (int k = 0; k < 2 * kThreads; ++k) partials_add(s_part, np, s_terms[k]);
+      __syncthreads();
+    }
+    if (tid == 0) s_sum = partials_round(s_part, np);
+  }
+  if (tid == 0) {
+    const StatAcc &t = s_w[0];
     tdgemm_block_stats st;
     st.mn = t.mn;
     st.mx = t.mx;
-    st.sumsq = csum_value(t.s);
+    st.sumsq = s_sum;
     st.n = (int64_t)vr * vc;
     *out = st;
   }
@@ -208,12 +244,6 @@ struct PlanArgs {
 
 __device__ __forceinline__ int srow(int W) { return W - 2; }   // s table row of W
 
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // TT: subblocks per lane the kernel is compiled for (T = ceil(nL / 64) <= TT).
 template <int TT>
 __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
@@ -247,10 +277,13 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
   double dopt[kMaxOpt][TT];
   int kopt[kMaxOpt][TT];
   int level[TT];
-  CSum sig{0.0, 0.0};
+  double sigv[TT];                                // signal terms of the Sec. 6 budget
+  // this wavefront's LDS: the entries of the bisection, or the terms of an exact sum
+  double *scr = sh_ent[threadIdx.x / kWave];
 #pragma unroll
   for (int t = 0; t < TT; ++t) {
     level[t] = 0;
+    sigv[t] = 0.0;
 #pragma unroll
     for (int v = 0; v < kMaxOpt; ++v) { dopt[v][t] = 0.0; kopt[v][t] = -1; }
     if (t >= T) continue;
@@ -259,7 +292,7 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
     const double L_eff = (double)min<int64_t>(pb.L, pb.K - l * pb.L);
     const BlockMoments ma = moments(a.stats_a[i * pb.nL + l]);
     const BlockMoments mb = moments(a.stats_b[l * pb.nJ + j]);
-    sig = csum_add(sig, (L_eff * (ma.sigma * ma.sigma)) * (mb.sigma * mb.sigma));
+    sigv[t] = (L_eff * (ma.sigma * ma.sigma)) * (mb.sigma * mb.sigma);
     if (!snr || ma.amax == 0.0 || mb.amax == 0.0) continue;   // D = 0
 #pragma unroll 1
     for (int v = 0; v < a.n_opt; ++v) {
@@ -278,18 +311,17 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
 
   // level of slot t after removing every entry ranked below `cut`
   auto total_at = [&](const int (&rank)[kMaxOpt - 1][TT], int cut) {
-    CSum tot{0.0, 0.0};
+    double dvs[TT];
 #pragma unroll
     for (int t = 0; t < TT; ++t) {
       int lv = 0;
 #pragma unroll
       for (int v = 0; v < kMaxOpt - 1; ++v) lv += (rank[v][t] < cut) ? 1 : 0;
-      double dv = 0.0;
+      dvs[t] = 0.0;
 #pragma unroll
-      for (int v = 0; v < kMaxOpt; ++v) if (lv == v) dv = dopt[v][t];
-      tot = csum_add(tot, dv);
+      for (int v = 0; v < kMaxOpt; ++v) if (lv == v) dvs[t] = dopt[v][t];
     }
-    return wave_csum(tot);
+    return wave_sum_exact<TT>(dvs, scr);
   };
 
   double budget = 0.0;
@@ -299,7 +331,8 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
     // equals) drops one level while the inner kernel keeps saving at least
     // accel * nL * units(W_max) units of MFMA work (units(W) = 12 - 12 / W, in
     // twelfths of a W = 1 product, exact for W in {1, 2, 3, 4}) and that
-    // D is positive.
+    // D is positive. An unavailable option (D >= kDUnavailable) drops whatever
+    // the constraint: its product cannot be formed.
     int own = 0;
 #pragma unroll
     for (int t = 0; t < TT; ++t)
@@ -332,7 +365,7 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
         if (od > bd || (od == bd && ol < bl)) { bd = od; bl = ol; bdelta = odl; }
       }
       if (bl == INT64_MAX || !(bd > 0.0)) break;
-      if ((double)(saved - bdelta) < target) break;
+      if (bd < kDUnavailable && (double)(saved - bdelta) < target) break;
       saved -= bdelta;
       if ((bl & (kWave - 1)) == lane) {
         const int tt = (int)(bl / kWave);
@@ -341,7 +374,7 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
       }
     }
   } else if (a.ctrl == TDGEMM_CTRL_SNR && n_ent > 0) {
-    budget = (a.tile ? a.tile[i * pb.nJ + j] : a.snr_lin) * wave_csum(sig);
+    budget = (a.tile ? a.tile[i * pb.nJ + j] : a.snr_lin) * wave_sum_exact<TT>(sigv, scr);
     // does every pair's D decrease strictly along its entries (and weakly to the floor)?
     bool mono = true;
 #pragma unroll
@@ -380,17 +413,21 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
             if (ds > de || (ds == de && ls < le)) rank[v][t] += (rank[v][t] != INT_MAX) ? 1 : 0;
           }
       }
-      int n_pos = 0;
+      // n_unav: entries with D >= kDUnavailable, ranked first; the greedy removes
+      // them whatever the budget
+      int n_pos = 0, n_unav = 0;
 #pragma unroll
       for (int v = 0; v < kMaxOpt - 1; ++v)
 #pragma unroll
-        for (int t = 0; t < TT; ++t)
+        for (int t = 0; t < TT; ++t) {
           n_pos += __popcll(__ballot(rank[v][t] != INT_MAX));
+          n_unav += __popcll(__ballot(rank[v][t] != INT_MAX && dopt[v][t] >= kDUnavailable));
+        }
       int cut;
       if (!(total_at(rank, n_pos) <= budget)) {
         cut = INT_MAX;                            // the greedy empties every entry
       } else {
-        int lo = 0, hi = n_pos;
+        int lo = n_unav, hi = n_pos;
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
           if (total_at(rank, mid) <= budget) hi = mid;
@@ -408,16 +445,14 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
       }
     } else {
       for (;;) {
-        CSum tot{0.0, 0.0};
+        double dvs[TT];
 #pragma unroll
         for (int t = 0; t < TT; ++t) {
-          double dv = 0.0;
+          dvs[t] = 0.0;
 #pragma unroll
-          for (int v = 0; v < kMaxOpt; ++v) if (level[t] == v) dv = dopt[v][t];
-          tot = csum_add(tot, dv);
+          for (int v = 0; v < kMaxOpt; ++v) if (level[t] == v) dvs[t] = dopt[v][t];
         }
-        const double total = wave_csum(tot);
-        if (!(total > budget)) break;
+        const double total = wave_sum_exact<TT>(dvs, scr);
         // candidate with the largest current D, lowest l among equals
         double bd = -INFINITY;
         int64_t bl = INT64_MAX;
@@ -437,6 +472,8 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
           if (od > bd || (od == bd && ol < bl)) { bd = od; bl = ol; }
         }
         if (bl == INT64_MAX) break;               // everything already at the lowest W
+        // within the budget, and no unavailable option left (they are the largest D)
+        if (!(total > budget) && bd < kDUnavailable) break;
         if ((bl & (kWave - 1)) == lane) {
           const int tt = (int)(bl / kWave);
 #pragma unroll
@@ -445,7 +482,7 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
       }
     }
   } else if (a.ctrl == TDGEMM_CTRL_SNR) {
-    budget = (a.tile ? a.tile[i * pb.nJ + j] : a.snr_lin) * wave_csum(sig);
+    budget = (a.tile ? a.tile[i * pb.nJ + j] : a.snr_lin) * wave_sum_exact<TT>(sigv, scr);
   }
 
   // Prop. 3 control: s(R_max, W) at the smallest grid R not below R_max (+inf

@@ -58,6 +58,19 @@ def compare_plan(gpu_pairs, gpu_budget, gpu_sa, gpu_sb, res, tiles):
             assert gpu_budget[i, j] == plan.budget[(i, j)]
 
 
+def assert_elementwise(got, want, A, B, tol, what="C"):
+    """|got - want| <= tol * (|A| |B|) element by element: the magnitude of the
+    terms that eq. (2) sums bounds the rounding differences of any summation
+    order (a zero row or column of A or B must then match exactly)."""
+    bound = tol * (np.abs(np.asarray(A, dtype=np.float64)) @ np.abs(np.asarray(B, dtype=np.float64)))
+    d = np.abs(np.asarray(got, dtype=np.float64) - np.asarray(want, dtype=np.float64))
+    bad = ~(d <= bound)
+    if bad.any():
+        k = np.unravel_index(np.argmax(np.where(bad, d - bound, -np.inf)), d.shape)
+        raise AssertionError(f"{what}: {int(bad.sum())} elements beyond tol {tol:g} x |A||B|; "
+                             f"worst at {k}: |diff| {d[k]:.3e} > {bound[k]:.3e}")
+
+
 def rel_err(a, b) -> float:
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)

@@ -102,6 +102,9 @@ def _desc(binding, **kw):
     ({"ctrl": 4}, 0), ({"ctrl": 4, "snr_db": -math.inf}, -1), ({"ctrl": 4, "fixed_rmax": -1.0}, -1),
     ({"ctrl": 4, "fixed_w": 3}, -1), ({"ctrl": 4, "snr_db": math.inf}, 0),
     ({"k_split": -1}, -1), ({"k_split": 3}, 0), ({"k_split": 1000}, 0),
+    # L * lda or L * ldb at 2^31 and above: beyond the fused kernel's 32-bit tile offsets
+    ({"lda": (1 << 31) // 64}, -2), ({"lda": (1 << 31) // 64 - 1}, 0),
+    ({"ldb": (1 << 31) // 128, "L": 128}, -2), ({"ldb": (1 << 31) // 128 - 1, "L": 128}, 0),
 ])
 def test_descriptor_validation(binding, lib, kw, status):
     d = _desc(binding, **kw)
@@ -207,3 +210,4 @@ def test_plan_query_rejects_null_plan(lib):
                   ctypes.POINTER(ctypes.c_int64)]
     snr, short = ctypes.c_double(1.0), ctypes.c_int64(5)
     assert f(None, ctypes.byref(snr), None, ctypes.byref(short)) == -1
+

@@ -245,3 +245,88 @@ def test_plan_query_vs_oracle(td, case):
     want_snr = math.inf if n_sum == 0.0 else 10.0 * math.log10(math.fsum(sig) / n_sum)
     assert (got_snr == want_snr) if math.isinf(want_snr) else abs(got_snr - want_snr) <= 1e-9
     log(f"[plan] query {name}: predicted SNR {got_snr:.3f} dB, W {got_hist.tolist()}, short {got_short}")
+
+
+def test_sums_at_rounding_boundaries(td):
+    """Exactly rounded sums by construction (statistics and the Sec. 6 budget).
+    Block (0, 0) of A holds 1, 2^-27, 2^-27, 2^-100: its exact sum of squares
+    1 + 2^-53 + 2^-200 lies just above the midpoint between 1 and 1 + 2^-52 and
+    rounds up; block (0, 1) holds 1, 2^-27, 2^-27 (an exact tie, to even: 1).
+    The single inner kernel's signal terms L s_a^2 s_b^2 are 1, 2^-54, 2^-54,
+    2^-200 (one nonzero element per block of A row 1 and B column 1), whose sum
+    rounds up too. A compensated sum rounded once gives 1 in both cases."""
+    L, M, K, N = 64, 128, 4 * 64, 128
+    rng = np.random.default_rng(2024)
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N))
+    A[:64, :64] = 0.0
+    A[0, :4] = [1.0, 2.0 ** -27, 2.0 ** -27, 2.0 ** -100]
+    A[:64, 64:128] = 0.0
+    A[5, 64:67] = [1.0, 2.0 ** -27, 2.0 ** -27]
+    # inner kernel (1, 1): A row block 1 and B column block 1 with one nonzero per block
+    ab = [(2.0 ** 9, 1.0), (2.0 ** -9, 2.0 ** -9), (2.0 ** -9, 2.0 ** -9), (2.0 ** -45, 2.0 ** -46)]
+    A[64:, :] = 0.0
+    B[:, 64:] = 0.0
+    for l, (a, b) in enumerate(ab):
+        A[64 + 3, l * 64 + 7] = a
+        B[l * 64 + 11, 64 + 2] = b
+    tabs = _calib("std", L, "sym")
+    cfg = oracle_cfg(L, "sym", "f64", "snr", 30.0, (1, 2), 2, 1.0, 127.0)
+    ref = pl.make_plan(A, B, cfg, calib=tabs)
+    assert ref.stats_a[0][0].sumsq == 1.0 + 2.0 ** -52
+    assert ref.stats_a[0][1].sumsq == 1.0
+    terms = [ct.signal_term(L, ref.stats_a[1][l], ref.stats_b[l][1]) for l in range(4)]
+    assert terms == [1.0, 2.0 ** -54, 2.0 ** -54, 2.0 ** -200]
+    assert ref.budget[(1, 1)] == 10.0 ** (-3.0) * (1.0 + 2.0 ** -52)
+    calib = td.DeviceCalib(tabs[2].r, {2: tabs[2].s})
+    Ad, Bd = to_dev(A), to_dev(B)
+    desc = td.make_desc(Ad, Bd, L=L, form="sym", prec="f64", ctrl="snr", snr_db=30.0, w_allowed=(1, 2))
+    plan = td.tdgemm_plan(desc, Ad, Bd, calib)
+    sa, sb, pairs, budget = td.tdgemm_plan_export(plan)
+    assert sa[0, 0]["sumsq"] == 1.0 + 2.0 ** -52 and sa[0, 1]["sumsq"] == 1.0
+    assert budget[1, 1] == ref.budget[(1, 1)]
+
+    class _Res:
+        pass
+    res = _Res()
+    res.plan = ref
+    compare_plan(pairs, budget, sa, sb, res, [(i, j) for i in range(2) for j in range(2)])
+    log("[plan] rounding-boundary sums: statistics and budget equal the exactly rounded values")
+
+
+@pytest.mark.parametrize("ctrl,target", [("accel", 1.0), ("snr", -math.inf)])
+def test_unavailable_option_always_dropped(td, ctrl, target):
+    """A calibration table with no usable W = 4 point: however loose the target
+    (F_kernel = 1, or S = -inf dB, an infinite budget), no pair may keep the
+    unavailable W = 4 option, whose product would add nothing to C. Records equal
+    the oracle's; C equals the oracle's bit for bit and stays close to A B."""
+    L, M, K, N = 64, 192, 6 * 64, 128
+    log(f"[plan] unavailable W = 4 under {ctrl} {target}")
+    A, B = _inputs("laplace", M, K, N, 515)
+    tabs = _calib("no_w4", L, "sym")
+    cfg = pl.Config(L=L, form="sym", prec="f64", ctrl=ctrl, snr_db=target, accel=target,
+                    w_allowed=(1, 2, 4))
+    ref = pl.make_plan(A, B, cfg, calib=tabs)
+    calib = td.DeviceCalib(tabs[2].r, {2: tabs[2].s, 4: tabs[4].s})
+    Ad, Bd = to_dev(A), to_dev(B)
+    desc = td.make_desc(Ad, Bd, L=L, form="sym", prec="f64", ctrl=ctrl, snr_db=target, accel=target,
+                        w_allowed=(1, 2, 4))
+    plan = td.tdgemm_plan(desc, Ad, Bd, calib)
+    sa, sb, pairs, budget = td.tdgemm_plan_export(plan)
+
+    class _Res:
+        pass
+    res = _Res()
+    res.plan = ref
+    nI, nL, nJ, _ = plan.dims
+    compare_plan(pairs, budget, sa, sb, res, [(i, j) for i in range(nI) for j in range(nJ)])
+    assert not np.any(pairs["w"] == 4)
+    assert np.all(pairs["d"] < ct.D_UNAVAILABLE)
+    C = torch.empty((M, N), dtype=torch.float64, device="cuda")
+    td.tdgemm_gemm(plan, Ad, Bd, C, fused=1)
+    got = C.cpu().numpy()
+    np.testing.assert_array_equal(got, pl.run(A, B, cfg, calib=tabs, plan=ref).C)
+    snr = pl.snr_db(got, A @ B)
+    log(f"[plan] unavailable W = 4 under {ctrl}: W {np.bincount(pairs['w'].ravel(), minlength=5).tolist()}, "
+        f"SNR {snr:.1f} dB")
+    assert snr > 25.0
