@@ -269,6 +269,24 @@ tdgemm_status tdgemm_calibrate(int32_t L, int32_t W, int32_t form, int32_t prec,
                                double *r_out, double *m_out, double *s_out, void *ws,
                                size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid allocation): tdgemm_plan followed by
+ * tdgemm_gemm(fused = 1) with the plan's workspace in a static device array of
+ * TDGEMM_NOALLOC_MAX_BYTES bytes per GPU instead of a caller workspace. It
+ * allocates neither device nor host memory and does not synchronise.
+ * desc, A, B, calib: as for tdgemm_plan; C: device output as for
+ * tdgemm_gemm(fused = 1). stream must belong to the current device.
+ * Errors (checked on the host before anything is enqueued):
+ *   TDGEMM_E_WORKSPACE    tdgemm_workspace_size(desc) > TDGEMM_NOALLOC_MAX_BYTES;
+ *   TDGEMM_E_UNSUPPORTED  desc->tile_target != NULL, or a block-scaled form;
+ *   otherwise those of tdgemm_plan and tdgemm_gemm.
+ * Every call on one GPU uses that GPU's one array, which keeps the last call's
+ * contents: calls that overlap on one GPU (on other streams or from other host
+ * threads) race and give wrong results. */
+#define TDGEMM_NOALLOC_MAX_BYTES ((size_t)32 << 20)
+tdgemm_status tdgemm_matmul_noalloc(const tdgemm_desc *desc, const void *A, const void *B,
+                                    const tdgemm_calib *calib, void *C, void *stream);
+
 /* Human-readable name of a status code (static storage). */
 const char *tdgemm_status_string(tdgemm_status status);
 

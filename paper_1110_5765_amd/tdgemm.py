@@ -89,6 +89,7 @@ def _load() -> ctypes.CDLL:
         "tdgemm_calibrate_workspace_size": (sz, [i32, i32]),
         "tdgemm_calibrate": (i32, [i32, i32, i32, i32, vp, i32, vp, vp, i32, dbl, vp, vp, vp,
                                    vp, sz, vp]),
+        "tdgemm_matmul_noalloc": (i32, [P(Desc), vp, vp, P(Calib), vp, vp]),
         "tdgemm_status_string": (ctypes.c_char_p, [i32]),
     }
     for name, (res, args) in sig.items():
@@ -326,6 +327,17 @@ def tdgemm_calibrate(L: int, W: int, form: str, prec: str, q, u_a: torch.Tensor,
                                  s.ctypes.data, _ptr(ws), ws.numel(), _stream(stream)),
            "tdgemm_calibrate")
     return r, m, s
+
+
+NOALLOC_MAX_BYTES = 32 << 20
+
+
+def tdgemm_matmul_noalloc(desc: Desc, A: torch.Tensor, B: torch.Tensor, calib: DeviceCalib | None,
+                          C: torch.Tensor, stream=None) -> None:
+    """tdgemm_plan + fused tdgemm_gemm with the library's static device workspace."""
+    cal = ctypes.byref(calib.struct) if calib is not None else None
+    _check(_LIB.tdgemm_matmul_noalloc(ctypes.byref(desc), _ptr(A), _ptr(B), cal, _ptr(C),
+                                      _stream(stream)), "tdgemm_matmul_noalloc")
 
 
 def tdgemm_status_string(status: int) -> str:

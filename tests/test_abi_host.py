@@ -211,3 +211,28 @@ def test_plan_query_rejects_null_plan(lib):
     snr, short = ctypes.c_double(1.0), ctypes.c_int64(5)
     assert f(None, ctypes.byref(snr), None, ctypes.byref(short)) == -1
 
+
+def test_noalloc_rejections_before_any_launch(binding, lib):
+    """tdgemm_matmul_noalloc checks on the host, before touching a device: an
+    invalid descriptor, a tile map or a block-scaled form, a workspace beyond the
+    static array, a missing calibration table."""
+    f = lib.tdgemm_matmul_noalloc
+    f.restype = ctypes.c_int32
+    dummy = ctypes.c_void_p(0x1000)   # never dereferenced: the checks fail first
+    cal = binding.Calib(1, 0x1000, 0x1000)
+
+    def call(d, calib=cal):
+        return f(ctypes.byref(d), dummy, dummy, ctypes.byref(calib) if calib is not None else None, dummy,
+                 None)
+
+    assert call(_desc(binding, M=-1)) == -1
+    d = _desc(binding)
+    nI = nJ = 256 // 64
+    tmap = (ctypes.c_double * (nI * nJ))(*([30.0] * (nI * nJ)))
+    d.tile_target = ctypes.cast(tmap, ctypes.c_void_p)
+    assert call(d) == -2
+    assert call(_desc(binding, prec=binding.I8, ctrl=binding.CTRL_SEPARABLE, fixed_w=1, L=128)) == -2
+    big = _desc(binding, M=4096, N=4096, K=4096, lda=4096, ldb=4096, ldc=4096, k_split=64)
+    assert binding.tdgemm_workspace_size(big) > binding.NOALLOC_MAX_BYTES
+    assert call(big) == -3
+    assert call(_desc(binding), None) == -4
