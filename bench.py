@@ -264,7 +264,9 @@ def run_sweep(args):
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(A, B, args)
-        log(f"[bench] oracle on the host: {cpu['value']:.4f} GFLOP/s ({cpu['sample']})")
+        log(f"[bench] oracle on the host ({cpu['cpu_model']}, {cpu['nproc']} CPUs): {cpu['value']:.4f} "
+            f"GFLOP/s on {cpu['cores']} processes, {cpu['value_1thread']:.4f} GFLOP/s on one thread "
+            f"({cpu['sample']})")
 
     out = {
         "metric": "effective GFLOP/s at fixed output SNR vs plain FP64 GEMM; % of FP64 MFMA peak",
@@ -874,54 +876,130 @@ def precision_cpu_baseline(A, B, corner: int = 1024):
     t_rest = max((t1 - t0) - t_stats, 0.0)
     f = n / corner
     total = t_stats * f + t_rest * f * f
+    model, ncpu = host_cpu()
     return {"value": 2.0 * n ** 3 / total / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "cpu_model": model, "nproc": ncpu,
             "sample": f"INT8 form on the {corner} x {n} by {n} x {corner} corner ({t1 - t0:.1f} s), "
                       f"statistics scaled by {f:g}, the rest by {f * f:g}"}
 
 
-def cpu_baseline(A, B, args):
-    """The oracle on the host: statistics of every block plus the full pipeline on a
-    few inner kernels, extrapolated to the whole product. Its calibration table
-    comes from the oracle's own measurement (untimed, like the GPU's)."""
-    import numpy as np
-    import workloads
-    from oracle import blocks as bk
-    from oracle import calibration as cal
-    from oracle import pipeline as pl
+def host_cpu() -> tuple[str, int]:
+    """(CPU model name, logical CPUs this process may run on)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
 
+
+_CPU_WORKER: dict = {}
+
+
+def _cpu_worker_init(dist, n, L, cfg, tabs):
+    """Spawned oracle worker: one BLAS thread, its own copy of the seeded inputs."""
     from threadpoolctl import threadpool_limits
 
-    L = args.L
-    n = A.shape[0]
-    with threadpool_limits(limits=1):
-        return _cpu_baseline(A, B, args, L, n)
+    import workloads
+    _CPU_WORKER["limits"] = threadpool_limits(limits=1)
+    A, B = workloads.sweep(dist, n=n)
+    _CPU_WORKER.update(A=A, B=B, L=L, cfg=cfg, tabs=tabs)
 
 
-def _cpu_baseline(A, B, args, L, n):
+def _cpu_ready(_):
+    return True
+
+
+def _cpu_stats_task(k):
+    """Statistics of block row k of A (k < nb) or block column k - nb of B."""
+    from oracle import blocks as bk
+    A, B, L = _CPU_WORKER["A"], _CPU_WORKER["B"], _CPU_WORKER["L"]
+    nb = bk.n_blocks(A.shape[0], L)
+    if k < nb:
+        return [bk.block_stats(A, k, l, L) for l in range(bk.n_blocks(A.shape[1], L))]
+    return [bk.block_stats(B, l, k - nb, L) for l in range(bk.n_blocks(B.shape[0], L))]
+
+
+def _cpu_tile_task(tile):
+    """Plan and pipeline of one inner kernel as the sub-problem of its A row panel
+    and B column panel; returns (seconds, of which the statistics of its blocks)."""
+    from oracle import blocks as bk
+    from oracle import pipeline as pl
+    A, B, L, cfg, tabs = (_CPU_WORKER[k] for k in ("A", "B", "L", "cfg", "tabs"))
+    i, j = tile
+    a, b = A[i * L:(i + 1) * L], B[:, j * L:(j + 1) * L]
+    t0 = time.perf_counter()
+    pl.run(a, b, cfg, tabs, plan=pl.make_plan(a, b, cfg, tabs))
+    t1 = time.perf_counter()
+    bk.all_block_stats(a, L)
+    bk.all_block_stats(b, L)
+    return t1 - t0, time.perf_counter() - t1
+
+
+def cpu_baseline(A, B, args):
+    """The oracle on the host, on one thread and on all the cores this process may
+    use. One thread: statistics of every block, then plan (options, pruning) and
+    pipeline for a sample of inner kernels, extrapolated to all of them. All
+    cores: spawned workers compute the statistics of all blocks (block rows of A,
+    block columns of B) and the sampled inner kernels in parallel; the tile phase
+    is extrapolated the same way. Its calibration table comes from the oracle's
+    own measurement (untimed, like the GPU's)."""
+    import multiprocessing as mp
+
     import numpy as np
+    from threadpoolctl import threadpool_limits
+
     import workloads
     from oracle import blocks as bk
     from oracle import calibration as cal
     from oracle import pipeline as pl
 
-    ua, ub = workloads.calib_uniforms(L)
-    tabs = {W: cal.calibrate(L, W, args.form, "f64", ua, ub, q_max=1 << 18)[0]
-            for W in (int(x) for x in args.w.split(",")) if W > 1}
-    cfg = pl.Config(L=L, form=args.form, prec="f64", ctrl="snr", snr_db=args.snr,
-                    w_allowed=tuple(int(x) for x in args.w.split(",")))
+    L, n = args.L, A.shape[0]
+    model, ncpu = host_cpu()
+    workers = max(1, min(16, ncpu))
+    ws_allowed = tuple(int(x) for x in args.w.split(","))
+    cfg = pl.Config(L=L, form=args.form, prec="f64", ctrl="snr", snr_db=args.snr, w_allowed=ws_allowed)
     nb = bk.n_blocks(n, L)
     rng = np.random.default_rng(0)
-    tiles = [(int(i), int(j)) for i, j in rng.integers(0, nb, (args.cpu_tiles, 2))]
-    t0 = time.perf_counter()
-    plan = pl.make_plan(A, B, cfg, tabs, tiles=tiles)
-    t1 = time.perf_counter()
-    pl.run(A, B, cfg, tabs, tiles=tiles, plan=plan)
-    t2 = time.perf_counter()
-    # make_plan = statistics of all blocks + options/pruning for the sampled tiles
-    total = (t1 - t0) + (t2 - t1) * (nb * nb) / len(tiles)
-    return {"value": 2.0 * n ** 3 / total / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": f"block statistics of all of A and B plus plan and pipeline for {len(tiles)} of "
-                      f"{nb * nb} inner kernels ({t2 - t0:.1f} s), extrapolated to all inner kernels"}
+    with threadpool_limits(limits=1):
+        ua, ub = workloads.calib_uniforms(L)
+        tabs = {W: cal.calibrate(L, W, args.form, "f64", ua, ub, q_max=1 << 18)[0] for W in ws_allowed if W > 1}
+        tiles = [(int(i), int(j)) for i, j in rng.integers(0, nb, (args.cpu_tiles, 2))]
+        t0 = time.perf_counter()
+        bk.all_block_stats(A, L)
+        bk.all_block_stats(B, L)
+        t1 = time.perf_counter()
+        plan = pl.make_plan(A, B, cfg, tabs, tiles=tiles)      # statistics again + options for the sample
+        t2 = time.perf_counter()
+        pl.run(A, B, cfg, tabs, tiles=tiles, plan=plan)
+        t3 = time.perf_counter()
+    t_stats = t1 - t0
+    t_tile = max((t2 - t1) - t_stats, 0.0) + (t3 - t2)        # options, pruning and pipeline of the sample
+    total1 = t_stats + t_tile * (nb * nb) / len(tiles)
+
+    ptiles = [(int(i), int(j)) for i, j in rng.integers(0, nb, (2 * workers, 2))]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers, initializer=_cpu_worker_init, initargs=(args.dist, n, L, cfg, tabs)) as pool:
+        pool.map(_cpu_ready, range(workers), chunksize=1)
+        p0 = time.perf_counter()
+        pool.map(_cpu_stats_task, range(2 * nb), chunksize=1)
+        p1 = time.perf_counter()
+        res = pool.map(_cpu_tile_task, ptiles, chunksize=1)
+        p2 = time.perf_counter()
+    rest = sum(t - s for t, s in res) / max(sum(t for t, _ in res), 1e-12)   # share beyond statistics
+    totalp = (p1 - p0) + (p2 - p1) * rest * (nb * nb) / len(ptiles)
+    flops = 2.0 * n ** 3
+    return {"value": round(flops / totalp / 1e9, 4), "unit": "GFLOP/s", "cores": workers, "kind": "oracle",
+            "cpu_model": model, "nproc": ncpu, "value_1thread": round(flops / total1 / 1e9, 4),
+            "sample": f"1 thread: statistics of all {2 * nb * nb} blocks ({t_stats:.1f} s) plus plan and "
+                      f"pipeline of {len(tiles)} of {nb * nb} inner kernels ({t_tile:.1f} s), extrapolated; "
+                      f"{workers} processes: all statistics ({p1 - p0:.1f} s) plus {len(ptiles)} inner "
+                      f"kernels ({p2 - p1:.1f} s, of which {100 * rest:.0f} % beyond their statistics), "
+                      f"extrapolated"}
 
 
 if __name__ == "__main__":
