@@ -14,9 +14,12 @@ form on the block structure of Sec. 2:
 * Per pair (i, l, j): r = sum_k qA[m, k] qB[k, n]. For INT8 the sum is exact
   (int64). For FP8 each product of two E4M3 values is exact and so is their
   sum in float64 (at most 43 significant bits), rounded once to float32.
-* Reverse companding and the l-sum of eq. (2), in float32: inv32 = float32(1 /
-  (c_A c_B)), C_ij = sum_l float32(r) * inv32, multiply then add, l ascending.
-  C is float32: the form accumulates in 32-bit arithmetic.
+* Reverse companding (eq. 5) and the l-sum of eq. (2), in float32: inv32 =
+  float32(1 / (c_A c_B)), and per output C = fma(float32(r), inv32, C) for l
+  ascending from C = 0 -- one correctly rounded fused multiply-add per pair,
+  i.e. an FMA chain over l (the paper fixes the rounding of neither step; one
+  rounding per pair is the plainest). C is float32: the form accumulates in
+  32-bit arithmetic.
 
 E4M3FN (OCP 8-bit floating point, format E4M3): 1 sign bit, 4 exponent bits
 with bias 7, 3 mantissa bits; exponent field 0 holds the subnormals m 2^-9;
@@ -32,6 +35,7 @@ import numpy as np
 
 from . import blocks as bk
 from . import control as ct
+from .fmachain import fma_matmul
 from .pipeline import Config
 
 FORMATS = ("i8", "e4m3")
@@ -161,7 +165,8 @@ def run(A: np.ndarray, B: np.ndarray, L: int, fmt: str, q: float, u_safe: float 
     C = np.zeros((nI * L, nJ * L), dtype=np.float32)
     for i in range(nI):
         for j in range(nJ):
-            acc = np.zeros((L, L), dtype=np.float32)
+            rs = np.zeros((nL, L, L), dtype=np.float32)      # float32(r) per l
+            invs = np.zeros(nL, dtype=np.float32)             # float32(1 / (c_A c_B)) per l
             for l in range(nL):
                 L_eff = bk.valid_extent(K, l, L)
                 o = block_scaled_option(L_eff, sa[i][l], sb[l][j], q, u_safe)
@@ -176,9 +181,12 @@ def run(A: np.ndarray, B: np.ndarray, L: int, fmt: str, q: float, u_safe: float 
                     r32 = r.astype(np.float32)
                 if keep_products:
                     products[(i, j, l)] = r if fmt == "i8" else r32
-                inv32 = np.float32(o.inv)
-                acc = acc + r32 * inv32
-            C[i * L:(i + 1) * L, j * L:(j + 1) * L] = acc
+                rs[l] = r32
+                invs[l] = np.float32(o.inv)
+            # per output, the FMA chain over l ascending: row (r_0 .. r_nL-1) by column (inv_0 ..)
+            rows = np.ascontiguousarray(rs.reshape(nL, L * L).T).reshape(L * L, 1, nL)
+            cols = np.ascontiguousarray(np.broadcast_to(invs.reshape(1, nL, 1), (L * L, nL, 1)))
+            C[i * L:(i + 1) * L, j * L:(j + 1) * L] = fma_matmul(rows, cols, "f32").reshape(L, L)
     return Result(sa, sb, scale_a, scale_b, options, qa, qb, products, C[:M, :N])
 
 

@@ -111,13 +111,19 @@ __global__ __launch_bounds__(kThreads) void k_quant8(Quant8Args a) {
 // buffered, next l prefetched in registers), multiplied on the matrix cores
 // (INT8 16x16x64 with exact INT32 results; FP8 16x16x128 with FP32 results),
 // and then either written out per pair (STAGED) or added to C as
-// float(r) * float(inv), l ascending.
-// At most 256 registers per lane, so that two workgroups (72 KB of LDS each)
+// C = fma(float(r), float(inv), C), l ascending.
+// At most 256 registers per lane, so that two workgroups (64 KB of LDS each)
 // share a CU and one's LDS waits and epilogue overlap the other's MFMAs.
+//
+// LDS rows are 128 bytes; the 16-byte chunk c of row r sits at chunk position
+// c ^ ((r >> 1) & 7). Sixteen lanes reading (or writing) 16 bytes each from
+// sixteen consecutive rows, or from two rows, then touch all 64 banks once.
+__device__ __forceinline__ int swz8(int r, int c16) { return (c16 ^ ((r >> 1) & 7)) * 16; }
+
 template <int FMT, bool STAGED>
 __global__ __launch_bounds__(kThreads, 2) void k_gemm8(Gemm8Args a) {
-  __shared__ __align__(16) uint8_t sa[2][kL8][kRow8];
-  __shared__ __align__(16) uint8_t sb[2][kL8][kRow8];
+  __shared__ __align__(16) uint8_t sa[2][kL8][kL8];
+  __shared__ __align__(16) uint8_t sb[2][kL8][kL8];
   const int64_t tile = blockIdx.x;
   const int64_t i = tile / a.nJ, j = tile - (tile / a.nJ) * a.nJ;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -139,67 +145,96 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm8(Gemm8Args a) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int ch = tid + kThreads * q, r = ch >> 3, c16 = ch & 7;
-      *reinterpret_cast<v4i *>(&sa[buf][r][c16 * 16]) = stage[q];
-      *reinterpret_cast<v4i *>(&sb[buf][r][c16 * 16]) = stage[4 + q];
+      *reinterpret_cast<v4i *>(&sa[buf][r][swz8(r, c16)]) = stage[q];
+      *reinterpret_cast<v4i *>(&sb[buf][r][swz8(r, c16)]) = stage[4 + q];
     }
   };
 
   typedef typename std::conditional<FMT == TDGEMM_I8, v4i, v4f>::type acc_t;
   acc_t acc[4][4];
   v4f cacc[4][4];
+  const acc_t zero = acc_t{0, 0, 0, 0};
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      acc[x][y] = acc_t{0, 0, 0, 0};
-      cacc[x][y] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int y = 0; y < 4; ++y) cacc[x][y] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  // The products of pair l into acc: fragments of A, then per 32-column half h
+  // of the wavefront's tile (y in {2h, 2h + 1}) the fragments of B and the MFMAs.
+  typedef typename std::conditional<FMT == TDGEMM_I8, v4i, v8i>::type frag_t;
+  constexpr int NKS = FMT == TDGEMM_I8 ? 2 : 1;           // k-steps per pair
+  frag_t fa[NKS][4];
+  auto read_a = [&](int buf) {
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int r = wr * 64 + x * 16 + li;
+        if constexpr (FMT == TDGEMM_I8) {
+          fa[ks][x] = *reinterpret_cast<const v4i *>(&sa[buf][r][swz8(r, ks * 4 + g)]);
+        } else {
+          const v4i lo = *reinterpret_cast<const v4i *>(&sa[buf][r][swz8(r, 2 * g)]);
+          const v4i hi = *reinterpret_cast<const v4i *>(&sa[buf][r][swz8(r, 2 * g + 1)]);
+          fa[ks][x] = v8i{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        }
+      }
+  };
+  auto mma_half = [&](int buf, auto hc) {
+    constexpr int h = decltype(hc)::value;
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      frag_t fb[2];
+#pragma unroll
+      for (int yy = 0; yy < 2; ++yy) {
+        const int r = wc * 64 + (2 * h + yy) * 16 + li;
+        if constexpr (FMT == TDGEMM_I8) {
+          fb[yy] = *reinterpret_cast<const v4i *>(&sb[buf][r][swz8(r, ks * 4 + g)]);
+        } else {
+          const v4i lo = *reinterpret_cast<const v4i *>(&sb[buf][r][swz8(r, 2 * g)]);
+          const v4i hi = *reinterpret_cast<const v4i *>(&sb[buf][r][swz8(r, 2 * g + 1)]);
+          fb[yy] = v8i{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        }
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int yy = 0; yy < 2; ++yy) {
+          const int y = 2 * h + yy;
+          // each pair's product starts from zero at its first k-step
+          if constexpr (FMT == TDGEMM_I8)
+            acc[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[ks][x], fb[yy], ks == 0 ? zero : acc[x][y],
+                                                              0, 0, 0);
+          else
+            acc[x][y] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fa[ks][x], fb[yy], zero, 0, 0, 0,
+                                                                          127, 0, 127);
+        }
     }
+  };
+  // C = fma(r, inv, C) for the half h of the pair just multiplied (eqs. 5, 2)
+  auto epi_half = [&](float inv, auto hc) {
+    constexpr int h = decltype(hc)::value;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          cacc[x][2 * h + yy][r] = __builtin_fmaf((float)acc[x][2 * h + yy][r], inv, cacc[x][2 * h + yy][r]);
+  };
+  const std::integral_constant<int, 0> H0;
+  const std::integral_constant<int, 1> H1;
 
   gload(0);
   sstore(0);
   __syncthreads();
   for (int64_t l = 0; l < a.nL; ++l) {
     const int buf = (int)(l & 1);
-    if (l + 1 < a.nL) gload(l + 1);
-    if constexpr (FMT == TDGEMM_I8) {
-#pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
-        v4i fa[4], fb[4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-          fa[x] = *reinterpret_cast<const v4i *>(&sa[buf][wr * 64 + x * 16 + li][ks * 64 + g * 16]);
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-          fb[y] = *reinterpret_cast<const v4i *>(&sb[buf][wc * 64 + y * 16 + li][ks * 64 + g * 16]);
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y)
-            acc[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[x], fb[y], acc[x][y], 0, 0, 0);
-      }
-    } else {
-      v8i fa[4], fb[4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        const uint8_t *p = &sa[buf][wr * 64 + x * 16 + li][g * 32];
-        const v4i lo = *reinterpret_cast<const v4i *>(p), hi = *reinterpret_cast<const v4i *>(p + 16);
-        fa[x] = v8i{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-      }
-#pragma unroll
-      for (int y = 0; y < 4; ++y) {
-        const uint8_t *p = &sb[buf][wc * 64 + y * 16 + li][g * 32];
-        const v4i lo = *reinterpret_cast<const v4i *>(p), hi = *reinterpret_cast<const v4i *>(p + 16);
-        fb[y] = v8i{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-      }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fa[x], fb[y], acc[x][y], 0, 0,
-                                                                        0, 127, 0, 127);
-    }
     const int64_t pair = (i * a.nJ + j) * a.nL + l;
+    if (l + 1 < a.nL) gload(l + 1);
+    read_a(buf);
     if constexpr (STAGED) {
+      mma_half(buf, H0);
+      mma_half(buf, H1);
 #pragma unroll
       for (int x = 0; x < 4; ++x)
 #pragma unroll
@@ -213,17 +248,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm8(Gemm8Args a) {
           }
     } else {
       const float inv = (float)a.pairs[pair].inv;
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) cacc[x][y][r] = cacc[x][y][r] + (float)acc[x][y][r] * inv;
+      mma_half(buf, H0);
+      mma_half(buf, H1);
+      epi_half(inv, H0);
+      epi_half(inv, H1);
     }
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] = acc_t{0, 0, 0, 0};
     if (l + 1 < a.nL) sstore(buf ^ 1);
     lds_barrier();
   }
@@ -242,7 +271,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm8(Gemm8Args a) {
   }
 }
 
-// C = sum_l float(R_pair) * float(inv_pair), l ascending, from staged products.
+// C = fma(float(R_pair), float(inv_pair), C), l ascending from 0, from staged products.
 template <int FMT>
 __global__ __launch_bounds__(kThreads) void k_scale_sum8(Gemm8Args a) {
   const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -256,7 +285,7 @@ __global__ __launch_bounds__(kThreads) void k_scale_sum8(Gemm8Args a) {
     const int64_t o = pair * (kL8 * kL8) + r * kL8 + c;
     const float rv = (FMT == TDGEMM_I8) ? (float)static_cast<const int32_t *>(a.in)[o]
                                         : static_cast<const float *>(a.in)[o];
-    acc = acc + rv * (float)a.pairs[pair].inv;
+    acc = __builtin_fmaf(rv, (float)a.pairs[pair].inv, acc);
   }
   static_cast<float *>(a.out)[m * a.ldc + n] = acc;
 }

@@ -1,5 +1,6 @@
 """Pins of the INT8 / FP8 block-scaled oracle (oracle/precision.py)."""
 import math
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -128,3 +129,44 @@ def test_fp8_rounding_bound_and_grid():
     codes = pr.codes(q, "e4m3")
     assert all(pr.e4m3_decode(int(c)) == x for c, x in zip(codes.ravel()[:500], q.ravel()[:500]))
     assert pr.exact_fp8_sums_fit(128)
+
+
+def _round_f32(x: Fraction) -> float:
+    """The float32 value nearest to the rational x (ties to even), exactly."""
+    if x == 0:
+        return 0.0
+    sign = -1 if x < 0 else 1
+    x = abs(x)
+    e = x.numerator.bit_length() - x.denominator.bit_length()   # 2^(e-1) <= x < 2^(e+1)
+    while x >= Fraction(2) ** (e + 1):
+        e += 1
+    while x < Fraction(2) ** e:
+        e -= 1
+    q = max(e, -126) - 23                                  # ulp of the binade (subnormals below 2^-126)
+    m = x / Fraction(2) ** q
+    n, r = divmod(m.numerator, m.denominator)
+    if 2 * r > m.denominator or (2 * r == m.denominator and n % 2 == 1):
+        n += 1
+    return sign * float(Fraction(n) * Fraction(2) ** q)
+
+
+def test_epilogue_is_one_fused_multiply_add_per_pair():
+    """Reverse companding and the l-sum: C = fma(float32(r), float32(1/(c_A c_B)), C)
+    for l ascending from 0, each step rounded once to float32 -- checked against
+    exact rational arithmetic, on outputs where multiply-then-add rounds differently."""
+    rng = np.random.default_rng(21)
+    L = 64
+    A = rng.laplace(0, 1, (L, 4 * L)) * rng.uniform(0.5, 3.0, (1, 4 * L))
+    B = rng.standard_normal((4 * L, L))
+    res = pr.run(A, B, L, "i8", 127.0)
+    invs = [np.float32(res.options[(0, 0, l)].inv) for l in range(4)]
+    differs = 0
+    for (m, n) in [(int(a), int(b)) for a, b in rng.integers(0, L, (40, 2))]:
+        acc, naive = 0.0, np.float32(0.0)
+        for l in range(4):
+            r = int(res.products[(0, 0, l)][m, n])
+            acc = _round_f32(Fraction(r) * Fraction(float(invs[l])) + Fraction(acc))
+            naive = naive + np.float32(r) * invs[l]
+        assert res.C[m, n] == np.float32(acc), (m, n)
+        differs += int(np.float32(acc) != naive)
+    assert differs > 0        # the sample tells the two readings apart
