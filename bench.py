@@ -81,7 +81,7 @@ def parse():
     ap.add_argument("--no-k-split", dest="k_split", action="store_false",
                     help="pca2d, scatter: one workgroup per inner kernel (no grouped l-sum)")
     ap.add_argument("--workload", default="sweep",
-                    choices=["sweep", "precision", "mlp", "scatter", "sweep-table", "fig7", "pca2d"])
+                    choices=["sweep", "precision", "mlp", "scatter", "sweep-table", "fig7", "pca2d", "accel"])
     ap.add_argument("--mlp-steps", type=int, default=200)
     ap.add_argument("--mlp-snr", type=float, default=20.0,
                     help="S_kernel of the packed FP32 products (W = 2 reaches about 20 dB)")
@@ -137,6 +137,8 @@ def main():
         return run_pca2d(args)
     if args.workload == "fig7":
         return run_fig7(args)
+    if args.workload == "accel":
+        return run_accel(args)
     return run_sweep(args)
 
 
@@ -443,6 +445,78 @@ def run_fig7(args):
         "snr_gap_sym_minus_asym_db": round(full["sym"]["snr_db"] - full["asym"]["snr_db"], 2),
         "table": rows,
         **plain,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_accel(args):
+    """Throughput control with W in {1, 2, 4} (4096^3 Gaussian FP64, L = 128): F_W
+    measured on the GPU (Sec. 5.B) and F_kernel from 0 to 100 %, pruned with the
+    measured saved-time units and with the nominal MFMA-work units."""
+    import torch
+
+    import workloads
+    from paper_1110_5765_amd import calib as cb
+    from paper_1110_5765_amd import tdgemm as td
+
+    n = args.n or 4096
+    L, form, ws_allowed = args.L, args.form, (1, 2, 4)
+    A, B = workloads.sweep(args.dist, n=n)
+    Ad = torch.from_numpy(A).cuda()
+    Bd = torch.from_numpy(B).cuda()
+    ref = torch.matmul(Ad, Bd)
+    calib, _, _ = cb.device_table(L, form, "f64", (2, 4), with_accel=True)
+    log(f"[bench] accel: measured F_W {calib.accel}, saved-time units {calib.units}")
+    flops = 2.0 * n ** 3
+    stream = torch.cuda.current_stream()
+    C = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    rows = []
+    for kind, units in (("measured", calib.units), ("nominal", None)):
+        for F in (0.0, 0.25, 0.5, 0.75, 1.0):
+            desc = td.make_desc(Ad, Bd, L=L, form=form, ctrl="accel", accel=F, w_allowed=ws_allowed,
+                                accel_units=units)
+            ws = torch.empty(td.tdgemm_workspace_size(desc), dtype=torch.uint8, device="cuda")
+            holder = {}
+
+            def step(ev, desc=desc, ws=ws, holder=holder):
+                if ev is not None:
+                    ev[0].record(stream)
+                holder["plan"] = td.tdgemm_plan(desc, Ad, Bd, calib, ws)
+                td.tdgemm_gemm(holder["plan"], Ad, Bd, C, fused=1)
+                if ev is not None:
+                    ev[1].record(stream)
+
+            ms, _ = timed_steps(torch, step, 2, max(5, args.steps // 2), 1)
+            _, _, pairs, _ = td.tdgemm_plan_export(holder["plan"])
+            wh = {int(w): int((pairs["w"] == w).sum()) for w in ws_allowed}
+            snr = snr_of(torch, C, ref)
+            rows.append({"units": kind, "F_kernel": F, "ms": round(ms, 4), "gflops": round(flops / ms / 1e6, 1),
+                         "snr_db": round(snr, 2), "w_histogram": wh})
+            log(f"[bench] accel {kind:8s} F={F:4.2f}: {ms:7.3f} ms  {flops / ms / 1e6:9.1f} GFLOP/s  "
+                f"SNR {snr:6.2f} dB  W {wh}")
+    main = next(r for r in rows if r["units"] == "measured" and r["F_kernel"] == 1.0)
+    out = {
+        "metric": "effective GFLOP/s at fixed output SNR vs plain FP64 GEMM; % of FP64 MFMA peak",
+        "value": main["gflops"],
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": max(5, args.steps // 2),
+        "warmup": 2,
+        "ms_per_step": main["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"throughput control: {n}^3 {args.dist} FP64, L = {L}, {form}, W in [1, 2, 4], "
+                               f"measured F_W, F_kernel = 100 % (all points in 'table')",
+                   "parallelism": "single GPU"},
+        "accel_measured": {str(k): round(v, 4) for k, v in calib.accel.items()},
+        "accel_units": {str(k): v for k, v in calib.units.items()},
+        "snr_db": main["snr_db"],
+        "table": rows,
         "roofline": None,
         "cpu_baseline": None,
     }

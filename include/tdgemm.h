@@ -66,7 +66,8 @@ typedef struct {
                                  no packing; the separable rounded operands [[c x]] (INT8,
                                  |.| <= sep_q <= 127) or E4M3FN(c x) (OCP FP8, sep_q <= 448)
                                  of every block are multiplied on the INT8 / FP8 matrix
-                                 cores per pair and C (float32) = sum_l r * float(1/(c_A c_B)).
+                                 cores per pair and C (float32) accumulates
+                                 fma(float(r), float(1/(c_A c_B)), C) over l ascending.
                                  Requires ctrl = SEPARABLE, fixed_w = 1 and L = 128. */
   int32_t L;                  /* inner-kernel size, eq. (1): 64, 96 or 128. The packings W
                                  must divide L: {1, 2, 4} at L = 64 and 128, {1, 2, 3} at
@@ -101,7 +102,8 @@ typedef struct {
   double u_safe;              /* eq. (15) safety term, normally 50 */
   double accel;               /* ACCEL: F_kernel in [0, 1]. Each inner kernel keeps saving at
                                  least accel * nL * (1 - 1/W_max) of the W = 1 MFMA work,
-                                 sum_l (1 - 1/W_l); with W in {1, 2} it is the fraction of
+                                 sum_l (1 - 1/W_l) (or, with accel_units, of the measured
+                                 time); with W in {1, 2} it is the fraction of
                                  subblock products that stay packed. Starting from W_max
                                  everywhere, the pair with the largest D (lowest l on ties)
                                  drops to the next allowed W while the constraint still holds
@@ -122,6 +124,14 @@ typedef struct {
                                  (more workgroups when M and N give few inner kernels). The
                                  workspace then holds ceil(nL / s) partial M x N results of
                                  prec. Not for the block-scaled forms (TDGEMM_E_UNSUPPORTED). */
+  int32_t accel_units[5];     /* ACCEL, optional: the time a pair saves at packing W against
+                                 W = 1, accel_units[W] for W = 2..4, in integer units (Sec. 5.B
+                                 keeps the acceleration F_W of every packing, measured off-line
+                                 on the target: units = round(scale (1 - 1/F_W)), scale <= 2^20).
+                                 Entries 0 and 1 must be 0, the others in [0, 2^20]. All zero:
+                                 nominal MFMA work, 12 - 12/W twelfths of a W = 1 product.
+                                 The constraint then reads sum_l units[W_l] >=
+                                 accel * nL * units[W_max]. Ignored in the other modes. */
 } tdgemm_desc;
 
 /* Representation-noise table s(R_max, W) of Sec. 4.B (eq. 18), device memory:
@@ -205,8 +215,8 @@ tdgemm_status tdgemm_pack(tdgemm_plan_t plan, const void *qA, const void *qB,
  * Block-scaled forms: a = qA, b = qB as written by tdgemm_compand. fused = 0:
  * out = the per-pair products r, n_pairs * L * L elements (int32 for I8, exact;
  * float32 for E4M3, the matrix cores' float32 sums), row-major per pair.
- * fused = 1: out = C (float32, ldc), C = sum_l float(r) * float(1/(c_A c_B)),
- * multiply then add, l ascending. */
+ * fused = 1: out = C (float32, ldc), C = fma(float(r), float(1/(c_A c_B)), C)
+ * for l ascending from C = 0 (one rounding per pair). */
 tdgemm_status tdgemm_gemm(tdgemm_plan_t plan, const void *a, const void *b, void *out,
                           int fused, void *stream);
 

@@ -182,21 +182,35 @@ def separable_option(W: int, L_eff: int, sa: BlockStats, sb: BlockStats, q: floa
     return PairOption(W, r_safe, c_a, c_b, q_a, q_b, r_safe, p, 1.0 / (c_a * c_b), d, np.nan, 0.0)
 
 
-def saved_units(W: int) -> int:
-    """MFMA work a pair saves at packing W, in twelfths of the W = 1 product:
-    12 (1 - 1/W), an integer for every W in {1, 2, 3, 4}."""
+def saved_units(W: int, units: dict | None = None) -> int:
+    """Work a pair saves at packing W against the W = 1 product, in integer units.
+
+    Nominal (units None): the MFMA work, in twelfths of the W = 1 product,
+    12 (1 - 1/W), an integer for every W in {1, 2, 3, 4}. Measured: Sec. 5.B
+    keeps the acceleration F_W of every packing, found by off-line timing on the
+    target; a pair then saves 1 - 1/F_W of its W = 1 time, which the caller
+    passes quantised to integers, units[W] (W = 1 saves 0)."""
+    if units is not None:
+        return 0 if W == 1 else int(units[W])
     if 12 % W:
         raise ValueError(f"W = {W} does not divide 12")
     return 12 - 12 // W
 
 
-def accel_target(nl: int, w_max: int, frac: float) -> float:
+def accel_units(f_w: dict, scale: int = 4096) -> dict:
+    """Integer units of saved time from measured accelerations F_W (Sec. 5.B):
+    round(scale (1 - 1/F_W)), at least 0 (a packing slower than W = 1 saves nothing)."""
+    return {int(W): max(0, int(round(scale * (1.0 - 1.0 / float(f))))) for W, f in f_w.items()}
+
+
+def accel_target(nl: int, w_max: int, frac: float, units: dict | None = None) -> float:
     """Required saved work of an inner kernel: the fraction `frac` of what
     packing every pair at w_max saves."""
-    return frac * nl * saved_units(w_max)
+    return frac * nl * saved_units(w_max, units)
 
 
-def prune_accel(options: list[dict[int, PairOption]], w_desc: list[int], frac: float) -> list[int]:
+def prune_accel(options: list[dict[int, PairOption]], w_desc: list[int], frac: float,
+                units: dict | None = None) -> list[int]:
     """Sec. 6 pruning under the throughput constraint F_kernel = frac.
 
     Starting from the maximum packing, the outcome with the highest distortion
@@ -206,13 +220,14 @@ def prune_accel(options: list[dict[int, PairOption]], w_desc: list[int], frac: f
     and once the highest remaining distortion is 0 (nothing to gain). With
     W in {1, 2}, frac is the fraction of subblock products that stay packed.
     An unavailable option (D >= D_UNAVAILABLE) drops whatever the constraint:
-    its product could not be formed.
+    its product could not be formed. units: measured saved-time units per W
+    (see saved_units); None counts nominal MFMA work.
     """
     nl = len(options)
     level = [0] * nl
     d = [options[l][w_desc[0]].d for l in range(nl)]
-    saved = sum(saved_units(w_desc[0]) for _ in range(nl))
-    target = accel_target(nl, w_desc[0], frac)
+    saved = sum(saved_units(w_desc[0], units) for _ in range(nl))
+    target = accel_target(nl, w_desc[0], frac, units)
     while True:
         cand = [l for l in range(nl) if level[l] < len(w_desc) - 1]
         if not cand:
@@ -224,7 +239,7 @@ def prune_accel(options: list[dict[int, PairOption]], w_desc: list[int], frac: f
         if not d[lstar] > 0.0:
             break
         w_now, w_next = w_desc[level[lstar]], w_desc[level[lstar] + 1]
-        after = saved - saved_units(w_now) + saved_units(w_next)
+        after = saved - saved_units(w_now, units) + saved_units(w_next, units)
         if after < target and d[lstar] < D_UNAVAILABLE:
             break
         saved = after

@@ -45,6 +45,9 @@ class Config:
     ctrl: str = "snr"            # 'snr' | 'accel' | 'fixed' | 'separable' | 'target'
     snr_db: float = 40.0
     accel: float = 1.0           # 'accel': required fraction F_kernel of the maximum saved work
+    # 'accel': saved-time units per W from measured accelerations F_W (Sec. 5.B),
+    # as control.accel_units gives them; None counts nominal MFMA work
+    accel_units: tuple | None = None
     # 'snr' / 'accel': optional per-inner-kernel targets, tile_targets[i][j] = S_kernel(i, j)
     # in dB or F_kernel(i, j) (Sec. 6); None uses snr_db / accel for every inner kernel
     tile_targets: tuple | None = None
@@ -126,7 +129,8 @@ def make_plan(A: np.ndarray, B: np.ndarray, cfg: Config, calib: dict | None = No
             ws = ct.prune(opts_l, w_desc, dk)
         elif cfg.ctrl == "accel":
             f_ij = cfg.accel if cfg.tile_targets is None else cfg.tile_targets[i][j]
-            ws = ct.prune_accel(opts_l, w_desc, f_ij)
+            units = None if cfg.accel_units is None else dict(cfg.accel_units)
+            ws = ct.prune_accel(opts_l, w_desc, f_ij, units)
         else:
             ws = [cfg.fixed_w] * nL
         for l in range(nL):

@@ -68,6 +68,9 @@ tdgemm_status validate_desc(const tdgemm_desc *d) {
   switch (d->ctrl) {
     case TDGEMM_CTRL_ACCEL:
       if (!(d->accel >= 0.0 && d->accel <= 1.0)) return TDGEMM_E_ARG;
+      if (d->accel_units[0] != 0 || d->accel_units[1] != 0) return TDGEMM_E_ARG;
+      for (int w = 2; w <= 4; ++w)
+        if (d->accel_units[w] < 0 || d->accel_units[w] > (1 << 20)) return TDGEMM_E_ARG;
       [[fallthrough]];
     case TDGEMM_CTRL_SNR: {
       if (d->ctrl == TDGEMM_CTRL_SNR && std::isnan(d->snr_db)) return TDGEMM_E_ARG;
@@ -224,6 +227,11 @@ hipError_t enqueue_plan(const tdgemm_plan_s &p, const void *A, const void *B,
     if (!with_options || (d.w_allowed & (1u << w))) pl.w_desc[pl.n_opt++] = w;
   if (!with_options) { pl.n_opt = 1; pl.w_desc[0] = d.fixed_w; }
   pl.accel = d.accel;
+  // saved work per pair and packing: measured units when given, else twelfths of
+  // the W = 1 MFMA work
+  const bool measured = d.accel_units[2] || d.accel_units[3] || d.accel_units[4];
+  for (int w = 0; w < 5; ++w)
+    pl.units[w] = w < 2 ? 0 : (measured ? d.accel_units[w] : 12 - 12 / w);
   pl.fixed_w = d.fixed_w;
   pl.block_scaled = block_scaled(d.prec) ? 1 : 0;
   pl.fixed_rmax = d.fixed_rmax;

@@ -38,6 +38,7 @@ struct PlanLaunch {
   int block_scaled;                    // INT8 / FP8 form: separable records with W = 1
   double fixed_rmax, sep_q, u_safe, snr_lin;
   double accel;                        // throughput constraint F_kernel (ACCEL control)
+  int units[5];                        // ACCEL: saved work per pair at packing W (units[1] = 0)
   const double *tile;                  // [nI][nJ] per inner kernel: 10^(-S/10) (SNR),
                                        // F_kernel (ACCEL) or 10^(S/10) (TARGET); nullptr:
                                        // snr_lin / accel / tgt_pow everywhere

@@ -238,6 +238,7 @@ struct PlanArgs {
   double fixed_rmax, sep_q, u_safe;
   double snr_lin;                      // 10^(-S/10), computed on the host
   double accel;                        // F_kernel of the throughput constraint
+  int units[5];                        // saved work per pair at packing W (units[1] = 0)
   const double *tile;                  // per-inner-kernel snr_lin / accel / tgt_pow, or nullptr
   double tgt_pow;                      // TARGET: 10^(S/10), computed on the host
 };
@@ -329,19 +330,20 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
   if (a.ctrl == TDGEMM_CTRL_ACCEL && n_ent > 0) {
     // Throughput constraint: the pair with the largest current D (lowest l among
     // equals) drops one level while the inner kernel keeps saving at least
-    // accel * nL * units(W_max) units of MFMA work (units(W) = 12 - 12 / W, in
-    // twelfths of a W = 1 product, exact for W in {1, 2, 3, 4}) and that
-    // D is positive. An unavailable option (D >= kDUnavailable) drops whatever
-    // the constraint: its product cannot be formed.
+    // accel * nL * units[W_max] and that D is positive. units[W] is the work a
+    // pair saves at W in integers: twelfths of a W = 1 product, 12 - 12 / W, or
+    // units of measured time from the accelerations F_W (Sec. 5.B). An
+    // unavailable option (D >= kDUnavailable) drops whatever the constraint:
+    // its product cannot be formed.
     int own = 0;
 #pragma unroll
     for (int t = 0; t < TT; ++t)
-      if (t < T && lane + (int64_t)kWave * t < pb.nL) own += 12 - 12 / a.w_desc[0];
+      if (t < T && lane + (int64_t)kWave * t < pb.nL) own += a.units[a.w_desc[0]];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) own += __shfl_xor(own, off);
     int saved = own;
     const double frac = a.tile ? a.tile[i * pb.nJ + j] : a.accel;
-    const double target = (frac * (double)pb.nL) * (double)(12 - 12 / a.w_desc[0]);
+    const double target = (frac * (double)pb.nL) * (double)a.units[a.w_desc[0]];
     for (;;) {
       double bd = -INFINITY;
       int64_t bl = INT64_MAX;
@@ -355,7 +357,7 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
 #pragma unroll
         for (int v = 0; v < kMaxOpt; ++v)
           if (level[t] == v) { dv = dopt[v][t]; wc = a.w_desc[v]; wn = a.w_desc[v + 1 < kMaxOpt ? v + 1 : v]; }
-        if (dv > bd || (dv == bd && l < bl)) { bd = dv; bl = l; bdelta = (12 - 12 / wc) - (12 - 12 / wn); }
+        if (dv > bd || (dv == bd && l < bl)) { bd = dv; bl = l; bdelta = a.units[wc] - a.units[wn]; }
       }
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
@@ -577,6 +579,7 @@ hipError_t launch_plan(const PlanLaunch &p, hipStream_t st) {
   a.u_safe = p.u_safe;
   a.snr_lin = p.snr_lin;
   a.accel = p.accel;
+  for (int w = 0; w < 5; ++w) a.units[w] = p.units[w];
   a.tile = p.tile;
   a.tgt_pow = p.tgt_pow;
   const int64_t tiles = p.pb.nI * p.pb.nJ;

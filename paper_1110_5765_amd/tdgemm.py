@@ -37,7 +37,8 @@ class Desc(ctypes.Structure):
                 ("fixed_w", ctypes.c_int32), ("snr_db", ctypes.c_double),
                 ("fixed_rmax", ctypes.c_double), ("sep_q", ctypes.c_double),
                 ("u_safe", ctypes.c_double), ("accel", ctypes.c_double),
-                ("tile_target", ctypes.c_void_p), ("k_split", ctypes.c_int32)]
+                ("tile_target", ctypes.c_void_p), ("k_split", ctypes.c_int32),
+                ("accel_units", ctypes.c_int32 * 5)]
 
 
 class Calib(ctypes.Structure):
@@ -152,7 +153,8 @@ def make_desc(A: torch.Tensor, B: torch.Tensor, *, L: int = 64, form: str = "sym
               prec: str | None = None, ctrl: str = "snr", snr_db: float = 40.0,
               w_allowed=(1, 2, 4), fixed_w: int = 2, fixed_rmax: float = float(2 ** 20),
               sep_q: float = 127.0, u_safe: float = 50.0, accel: float = 1.0,
-              ldc: int | None = None, tile_target=None, k_split: int = 1) -> Desc:
+              ldc: int | None = None, tile_target=None, k_split: int = 1,
+              accel_units: dict | None = None) -> Desc:
     M, K = A.shape
     K2, N = B.shape
     if K != K2:
@@ -179,6 +181,9 @@ def make_desc(A: torch.Tensor, B: torch.Tensor, *, L: int = 64, form: str = "sym
     d.u_safe = u_safe
     d.accel = accel
     d.k_split = k_split
+    if accel_units is not None:           # {W: saved-time units} from measured F_W
+        for w, u in accel_units.items():
+            d.accel_units[int(w)] = int(u)
     if tile_target is not None:
         # host array nI x nJ of per-inner-kernel targets (S in dB or F_kernel); the
         # descriptor keeps it alive for tdgemm_plan

@@ -84,6 +84,8 @@ def _desc(binding, **kw):
     d.sep_q = 127.0
     d.u_safe = 50.0
     for k, v in kw.items():
+        if k == "accel_units":
+            v = (ctypes.c_int32 * 5)(*v)
         setattr(d, k, v)
     return d
 
@@ -105,6 +107,10 @@ def _desc(binding, **kw):
     # L * lda or L * ldb at 2^31 and above: beyond the fused kernel's 32-bit tile offsets
     ({"lda": (1 << 31) // 64}, -2), ({"lda": (1 << 31) // 64 - 1}, 0),
     ({"ldb": (1 << 31) // 128, "L": 128}, -2), ({"ldb": (1 << 31) // 128 - 1, "L": 128}, 0),
+    # measured saved-time units of the throughput control (Sec. 5.B F_W)
+    ({"ctrl": 3, "accel": 0.5, "accel_units": (0, 0, 1365, 0, 2000)}, 0),
+    ({"ctrl": 3, "accel_units": (0, 7, 1365, 0, 2000)}, -1), ({"ctrl": 3, "accel_units": (0, 0, -1, 0, 0)}, -1),
+    ({"ctrl": 3, "accel_units": (0, 0, 1 << 21, 0, 0)}, -1), ({"accel_units": (0, 7, 0, 0, 0)}, 0),
 ])
 def test_descriptor_validation(binding, lib, kw, status):
     d = _desc(binding, **kw)

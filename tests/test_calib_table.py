@@ -71,3 +71,17 @@ def test_cache_is_used_without_measuring(cal, tmp_path, monkeypatch):
     s = dev.s.numpy().reshape(3, -1)
     assert s[0].tobytes() == table[2].tobytes() and s[2].tobytes() == table[4].tobytes()
     assert np.all(np.isinf(s[1]))             # W = 3 not in the table
+
+
+def test_accel_round_trip_and_units(cal, tmp_path):
+    """F_W kept beside the table (Sec. 5.B) round-trips exactly; the integer units
+    of the throughput control are round(4096 (1 - 1/F_W)), at least 0."""
+    r, table = _table(cal, 128, "f64", (2, 4))
+    p = str(tmp_path / "t.json")
+    acc = {2: 1.3312345678, 4: 1.9}
+    cal.write_table(p, 128, "sym", "f64", r, table, acc)
+    assert cal.read_accel(p) == acc
+    cal.write_table(p, 128, "sym", "f64", r, table)
+    assert cal.read_accel(p) is None
+    assert cal.accel_units({2: 2.0, 3: 1.0, 4: 0.5}) == {2: 2048, 3: 0, 4: 0}
+    assert cal.accel_units(acc) == {2: round(4096 * (1 - 1 / 1.3312345678)), 4: round(4096 * (1 - 1 / 1.9))}

@@ -330,3 +330,49 @@ def test_unavailable_option_always_dropped(td, ctrl, target):
     log(f"[plan] unavailable W = 4 under {ctrl}: W {np.bincount(pairs['w'].ravel(), minlength=5).tolist()}, "
         f"SNR {snr:.1f} dB")
     assert snr > 25.0
+
+
+@pytest.mark.parametrize("units,frac", [({2: 1365, 4: 1800}, 0.6), ({2: 1365, 4: 900}, 0.8),
+                                        ({2: 2048, 4: 3072}, 0.35)])
+def test_accel_measured_units_parity(td, units, frac):
+    """Throughput control with measured saved-time units per packing (Sec. 5.B F_W):
+    records bit-exact to the oracle fed the same units, and the product too."""
+    L, M, K, N = 64, 192, 10 * 64, 128
+    log(f"[plan] ACCEL with measured units {units}, F = {frac}")
+    A, B = _inputs("laplace", M, K, N, 600 + units[4])
+    tabs = _calib("std", L, "sym")
+    cfg = pl.Config(L=L, form="sym", prec="f64", ctrl="accel", accel=frac, w_allowed=(1, 2, 4),
+                    accel_units=tuple(sorted(units.items())))
+    ref = pl.make_plan(A, B, cfg, calib=tabs)
+    calib = td.DeviceCalib(tabs[2].r, {2: tabs[2].s, 4: tabs[4].s})
+    Ad, Bd = to_dev(A), to_dev(B)
+    desc = td.make_desc(Ad, Bd, L=L, form="sym", prec="f64", ctrl="accel", accel=frac, w_allowed=(1, 2, 4),
+                        accel_units=units)
+    plan = td.tdgemm_plan(desc, Ad, Bd, calib)
+    sa, sb, pairs, budget = td.tdgemm_plan_export(plan)
+
+    class _Res:
+        pass
+    res = _Res()
+    res.plan = ref
+    nI, nL, nJ, _ = plan.dims
+    compare_plan(pairs, budget, sa, sb, res, [(i, j) for i in range(nI) for j in range(nJ)])
+    nominal = pl.make_plan(A, B, pl.Config(L=L, form="sym", prec="f64", ctrl="accel", accel=frac,
+                                           w_allowed=(1, 2, 4)), calib=tabs)
+    differ = sum(ref.chosen[k].W != nominal.chosen[k].W for k in ref.chosen)
+    C = torch.empty((M, N), dtype=torch.float64, device="cuda")
+    td.tdgemm_gemm(plan, Ad, Bd, C, fused=1)
+    np.testing.assert_array_equal(C.cpu().numpy(), pl.run(A, B, cfg, calib=tabs, plan=ref).C)
+    log(f"[plan] measured units: W {np.bincount(pairs['w'].ravel(), minlength=5).tolist()}, "
+        f"{differ} pairs differ from the nominal-unit plan")
+
+
+def test_measured_accelerations(td):
+    """F_W measured on the GPU path (Sec. 5.B): packing saves time at W = 2 and 4
+    (L = 128, symmetric, FP64), and a plan with the derived units matches the oracle."""
+    from paper_1110_5765_amd import calib as cb
+    f = cb.measure_accel(128, "sym", "f64", (2, 4), n=2048, reps=5)
+    units = cb.accel_units(f)
+    log(f"[plan] measured F_W at L = 128 sym f64, 2048^3: {f}, units {units}")
+    assert all(1.0 < f[W] < 2.0 * W for W in (2, 4))
+    assert all(units[W] > 0 for W in (2, 4))

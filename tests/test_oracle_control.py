@@ -354,3 +354,39 @@ def test_grouped_l_sum():
         assert np.max(np.abs(got - one)) <= 1e-12 * np.max(np.abs(one))
     with pytest.raises(ValueError):
         pl.group_size(9, 0)
+
+
+def test_accel_units_from_measured_accelerations():
+    """Sec. 5.B keeps the measured acceleration F_W of each packing: a pair at W
+    saves 1 - 1/F_W of its W = 1 time, quantised to integer units."""
+    u = ct.accel_units({2: 2.0, 3: 4.0 / 3.0, 4: 1.0, 5: 0.8}, scale=4096)
+    assert u == {2: 2048, 3: 1024, 4: 0, 5: 0}
+    assert ct.saved_units(1, u) == 0 and ct.saved_units(3, u) == 1024
+
+
+@pytest.mark.parametrize("u2,u4", [(1365, 2000), (1365, 1000), (2048, 3072), (500, 500)])
+def test_prune_accel_with_measured_units(u2, u4):
+    """With measured units (W = 4 may save more or less than W = 2): the result
+    meets the constraint, and the greedy's next move (the highest current D that
+    can still drop) would either break it or gain time; W in {1, 2} keeps the
+    fraction of packed pairs whatever the unit."""
+    rng = np.random.default_rng(u2 + u4)
+    units = {2: u2, 4: u4}
+    for trial in range(150):
+        n = int(rng.integers(1, 7))
+        d2 = rng.exponential(1.0, n) + 0.01
+        d4 = d2 + rng.exponential(3.0, n)
+        opts = [{4: _opt(4, float(d4[l])), 2: _opt(2, float(d2[l])), 1: _opt(1, 0.0)} for l in range(n)]
+        frac = float(rng.uniform())
+        w = ct.prune_accel(opts, [4, 2, 1], frac, units)
+        saved = sum(ct.saved_units(x, units) for x in w)
+        target = ct.accel_target(n, 4, frac, units)
+        assert saved >= target
+        cur = [opts[l][w[l]].d for l in range(n)]
+        cand = [l for l in range(n) if w[l] != 1]
+        if cand:
+            l = max(cand, key=lambda x: (cur[x], -x))
+            nxt = {4: 2, 2: 1}[w[l]]
+            assert saved - ct.saved_units(w[l], units) + ct.saved_units(nxt, units) < target
+        two = [{2: _opt(2, float(d2[l])), 1: _opt(1, 0.0)} for l in range(n)]
+        assert ct.prune_accel(two, [2, 1], frac, units) == ct.prune_accel(two, [2, 1], frac)
