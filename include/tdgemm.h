@@ -40,7 +40,7 @@ extern "C" {
 typedef enum {
   TDGEMM_OK = 0,
   TDGEMM_E_ARG = -1,          /* invalid argument or shape */
-  TDGEMM_E_UNSUPPORTED = -2,  /* valid but not implemented (e.g. W = 4 at L = 96) */
+  TDGEMM_E_UNSUPPORTED = -2,  /* valid but not implemented (e.g. L = 80) */
   TDGEMM_E_WORKSPACE = -3,    /* workspace missing or too small */
   TDGEMM_E_CALIB = -4,        /* calibration table missing or malformed */
   TDGEMM_E_HIP = -5           /* a HIP runtime call failed */
@@ -70,8 +70,8 @@ typedef struct {
                                  fma(float(r), float(1/(c_A c_B)), C) over l ascending.
                                  Requires ctrl = SEPARABLE, fixed_w = 1 and L = 128. */
   int32_t L;                  /* inner-kernel size, eq. (1): 64, 96 or 128. The packings W
-                                 must divide L: {1, 2, 4} at L = 64 and 128, {1, 2, 3} at
-                                 L = 96 (W = 4 at L = 96: TDGEMM_E_UNSUPPORTED) */
+                                 must divide L: {1, 2, 4} at L = 64 and 128, {1, 2, 3, 4}
+                                 at L = 96 (the double-precision set of Sec. 7) */
   int32_t form;               /* TDGEMM_SYM or TDGEMM_ASYM */
   int32_t ctrl;               /* TDGEMM_CTRL_*:
                                  SNR: Sec. 5.B / Sec. 6 control to snr_db per inner kernel;
@@ -90,9 +90,9 @@ typedef struct {
                                         eq. (26) companders, the highest SNR at fixed_rmax. */
   uint32_t w_allowed;         /* SNR / ACCEL: bit w set => packing W = w allowed; bit 1
                                  (W = 1, native arithmetic) must be set; W in {1, 2, 4}, or
-                                 {1, 2, 3} at L = 96 */
-  int32_t fixed_w;            /* FIXED / SEPARABLE / TARGET: W in {1, 2, 4}, or {1, 2, 3} at
-                                 L = 96 */
+                                 any of {1, 2, 3, 4} at L = 96 */
+  int32_t fixed_w;            /* FIXED / SEPARABLE / TARGET: W in {1, 2, 4}, or {1, 2, 3, 4}
+                                 at L = 96 */
   double snr_db;              /* SNR mode: S_kernel(i, j) in dB for every inner kernel
                                  (Sec. 6); +inf requests native precision everywhere.
                                  TARGET: the expected subblock SNR in dB (not -inf; +inf

@@ -20,13 +20,11 @@ constexpr int64_t kMaxTileSpan = int64_t(1) << 31;   // L * lda and L * ldb must
 
 bool valid_l(int L) { return L == 64 || L == 96 || L == 128; }
 
-// Packings a block size supports: W divides L (eq. 1) and the kernels keep
-// whole MFMA steps: {1, 2, 4} at L = 64 and 128, {1, 2, 3} at L = 96.
-// E_ARG for a W outside {1, ..., 4} or one that does not divide L, and
-// E_UNSUPPORTED for W = 4 at L = 96.
+// Packings a block size supports: W divides L (eq. 1): {1, 2, 4} at L = 64 and
+// 128, {1, 2, 3, 4} at L = 96. E_ARG for a W outside {1, ..., 4} or one that
+// does not divide L.
 tdgemm_status check_w(int w, int L) {
   if (w < 1 || w > 4 || L % w != 0) return TDGEMM_E_ARG;
-  if (L == 96 && w == 4) return TDGEMM_E_UNSUPPORTED;
   return TDGEMM_OK;
 }
 
@@ -152,6 +150,14 @@ tdg::GemmOperands operands_of(const tdgemm_plan_s *p) {
   g.tb = p->desc.trans_b != 0;
   g.pairs = reinterpret_cast<const tdgemm_pair *>(p->ws + p->ly.off_pairs);
   g.gsize = p->ly.gsize;
+  const tdgemm_desc &d = p->desc;
+  g.wmax = 1;
+  if (d.ctrl == TDGEMM_CTRL_SNR || d.ctrl == TDGEMM_CTRL_ACCEL) {
+    for (int w = 2; w <= 4; ++w)
+      if (d.w_allowed & (1u << w)) g.wmax = w;
+  } else {
+    g.wmax = d.fixed_w;
+  }
   return g;
 }
 
@@ -521,6 +527,7 @@ tdgemm_status tdgemm_calibrate(int32_t L, int32_t W, int32_t form, int32_t prec,
   g.pb.lda = g.pb.ldb = g.pb.ldc = L;
   g.pb.nI = n_inst; g.pb.nJ = 1; g.pb.nL = 1;
   g.gsize = 1;
+  g.wmax = W;
   g.pb.L = L;
   g.in_dtype = prec; g.prec = prec; g.form = form; g.ta = g.tb = false;
   g.pairs = pairs_w;

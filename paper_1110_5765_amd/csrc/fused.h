@@ -60,9 +60,10 @@ __device__ __forceinline__ void owner_of_packed_row(int ml, int W, int &g, int &
 
 // L = 96: lane group g of a wavefront owns the 24 consecutive tile rows
 // 24 g .. 24 g + 23 (slot (a, g, r) holds row 24 g + 4 a + r), so the W
-// consecutive rows of an asymmetric word (W in {1, 2, 3}) stay in one lane.
+// consecutive rows of an asymmetric word (W in {1, 2, 3, 4}) stay in one lane.
 // Packed row mb (W = 1: tile row) goes to the MFMA position that yields its
-// first slot: k = mb mod (24 / W) counts the words of lane group g.
+// first slot: k = mb mod (24 / W) counts the words of lane group g. At W = 4
+// the six words of a lane group fill the first row block and half the second.
 template <typename PT, int W>
 __device__ __forceinline__ int lds_row_of96(int mb) {
   constexpr int per = 24 / W;
@@ -77,18 +78,23 @@ __device__ __forceinline__ int lds_row_of(int m, int W) {
   return (m & ~15) + mfma_pos<PT>(g, r);
 }
 
-template <typename IT, typename PT, int L, int FORM, bool TA, bool TB>
+// K48 (L = 96 only): chunks of 48 raw columns, which are whole MFMA k-steps for
+// every W in {1, 2, 3, 4}; launched when a plan may hold W = 4. Without it L = 96
+// runs 24-column chunks and W in {1, 2, 3}.
+template <typename IT, typename PT, int L, int FORM, bool TA, bool TB, bool K48 = false>
 struct Fused {
   static constexpr bool L96 = L == 96;
+  static_assert(!K48 || L96, "48-column chunks are the L = 96 variant with W = 4");
   static constexpr int TN = L96 ? 96 : 64;  // output columns per workgroup
   static constexpr int NT = 4 * L;        // threads: L / 16 wavefronts
   static constexpr int WC = L96 ? 6 : 4;  // wavefront columns, 16 output columns each
   static constexpr int RB = L96 ? 6 : 4;  // 16-row blocks per wavefront
   static constexpr int CB = 1;            // 16-column blocks per wavefront
-  static constexpr int KC = (L == 64) ? 16 : (L96 ? 24 : 32);  // raw inner columns per chunk
+  static constexpr int KC = (L == 64) ? 16 : (L96 ? (K48 ? 48 : 24) : 32);  // raw inner columns per chunk
   static constexpr int VA = KC * L / NT;  // raw A values per thread per chunk
   static constexpr int VB = KC * TN / NT; // raw B values per thread per chunk
-  static constexpr int WMAX = L96 ? 3 : 4;  // packings: {1, 2, WMAX}
+  static constexpr int WMAX = (L96 && !K48) ? 3 : 4;  // packings: {1, 2, WMAX}, and 3 at L = 96
+  static constexpr bool HAS3 = L96;
   // packed accumulator sets: two let a pair's unpack overlap the next pair's
   // MFMAs; with one (L = 96, six row blocks per wavefront) the unpack runs
   // before them
@@ -98,8 +104,12 @@ struct Fused {
   // column g (A) or column lc of rows g (B). With SA = KC + 2 (2 mod 32) the 32
   // A reads start on distinct even banks; with SB = TN + 16 (16 mod 32) the two
   // B rows fall on opposite halves of the banks.
+  // K48: B rows are TN elements without padding (the two tiles would exceed the
+  // 160 KB of LDS); element (k, n) sits at column n ^ 16 (k & 1) instead, which
+  // puts the two B rows of a fragment read on opposite halves of the banks.
   static constexpr int SA = KC + 2;
-  static constexpr int SB = TN + 16;
+  static constexpr int SB = K48 ? TN : TN + 16;
+  static constexpr int bcol(int k, int n) { return K48 ? (n ^ ((k & 1) << 4)) : n; }
   static constexpr int NCH = L / KC;      // chunks per pair
   // Symmetric form, A stored as given: four consecutive threads share a row and
   // thread i of the four holds columns 4i..4i+3 (and 4i+16..4i+19 when a chunk
@@ -114,10 +124,13 @@ struct Fused {
   static constexpr int PF = L96 ? 1 : 2;
   typedef typename Mfma<PT>::Acc Acc;
   static_assert(VA * NT == KC * L && VB * NT == KC * TN, "loads must cover a chunk");
-  static_assert(KC % (4 * WMAX) == 0 && KC % 8 == 0, "packed chunk depth: whole k-steps");
-  static_assert(VA % WMAX == 0 && VA % 2 == 0 && VB % WMAX == 0 && VB % 2 == 0,
+  static_assert(KC % (4 * WMAX) == 0 && KC % 8 == 0 && (!HAS3 || KC % 12 == 0),
+                "packed chunk depth: whole k-steps");
+  static_assert(VA % WMAX == 0 && VA % 2 == 0 && VB % WMAX == 0 && VB % 2 == 0 &&
+                (!HAS3 || (VA % 3 == 0 && VB % 3 == 0)),
                 "a thread's raw values form whole packed words");
-  static_assert(RB % WMAX == 0 && RB % 2 == 0, "asymmetric words: whole row blocks");
+  static_assert(L96 ? (RB % 6 == 0) : (RB % WMAX == 0 && RB % 2 == 0),
+                "asymmetric words: whole row blocks (L = 96, W = 4: one and a half)");
   static_assert(NT == 64 * WC * (L / (16 * RB)), "wavefront grid covers the tile");
 
   struct Smem {
@@ -238,9 +251,11 @@ struct Fused {
         PT acc = compand<W>(rb[S][u * W + W - 1], cb);
 #pragma unroll
         for (int s = W - 2; s >= 0; --s) acc = __builtin_fma(acc, zi, compand<W>(rb[S][u * W + s], cb));
-        sm.b[buf][(b_k / W + u) * SB + b_n] = acc;
+        const int k = b_k / W + u;
+        sm.b[buf][k * SB + bcol(k, b_n)] = acc;
       } else {
-        sm.b[buf][(b_k + u) * SB + b_n] = compand<W>(rb[S][u], cb);
+        const int k = b_k + u;
+        sm.b[buf][k * SB + bcol(k, b_n)] = compand<W>(rb[S][u], cb);
       }
     }
   }
@@ -260,14 +275,15 @@ struct Fused {
 
   // The chunk's MFMAs into accumulator set P: packed depth KC / W (symmetric)
   // or KC (asymmetric, W = 1). Wavefront (wr, wc) multiplies packed row blocks
-  // of its 64 output rows by its column blocks.
+  // of its 64 output rows by its column blocks. B fragment rows are 4 ks + lg,
+  // of the parity of lg.
   template <int W, int P>
   __device__ __forceinline__ void mma(int buf) {
     constexpr bool SYMW = (FORM == TDGEMM_SYM) || W == 1;
     constexpr int NKS = SYMW ? KC / (4 * W) : KC / 4;
-    constexpr int RBN = SYMW ? RB : RB / W;
+    constexpr int RBN = SYMW ? RB : (RB + W - 1) / W;
     const PT *as = sm.a[buf] + (16 * RBN * wr + lc) * SA + lg;
-    const PT *bs = sm.b[buf] + lg * SB + wcol + lc;
+    const PT *bs = sm.b[buf] + lg * SB + lc;
     // one fragment set: the reads of k-step ks + 1 go out right after the
     // MFMAs of ks are issued and return while those execute
     static_for<0, NKS>([&](auto ksc) {
@@ -276,7 +292,7 @@ struct Fused {
 #pragma unroll
       for (int a = 0; a < RBN; ++a) af[a] = as[16 * a * SA + 4 * ks];
 #pragma unroll
-      for (int b = 0; b < CB; ++b) bf[b] = bs[4 * ks * SB + 16 * b];
+      for (int b = 0; b < CB; ++b) bf[b] = bs[4 * ks * SB + bcol(lg, wcol + 16 * b)];
 #pragma unroll
       for (int a = 0; a < RBN; ++a)
 #pragma unroll
@@ -307,12 +323,13 @@ struct Fused {
             accC[a][b][r] = accC[a][b][r] + rr * inv;
           }
       } else if (L96) {                          // eqs. (13)-(14): W rows per word
-        // word k = 4 a + r of a lane group yields its rows W k + s, in the
-        // slots (W k + s) / 4, register (W k + s) mod 4
+        // word k = 4 a + r of a lane group (k < 24 / W) yields its rows W k + s,
+        // in the slots (W k + s) / 4, register (W k + s) mod 4
 #pragma unroll
-        for (int a = 0; a < RB / W; ++a)
+        for (int a = 0; a < (RB + W - 1) / W; ++a)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
+            if (4 * a + r >= 24 / W) continue;
             PT t = accR[P][a][b][r];
 #pragma unroll
             for (int sl = 0; sl < W; ++sl) {
@@ -380,21 +397,30 @@ struct Fused {
   __device__ __forceinline__ void store_any(int buf, const PairState &ps) {
     if (ps.w == 2) store<2, S>(buf, ps.ca, ps.cb, ps.z, ps.zi);
     else if (ps.w == 1) store<1, S>(buf, ps.ca, ps.cb, ps.z, ps.zi);
-    else store<WMAX, S>(buf, ps.ca, ps.cb, ps.z, ps.zi);
+    else if constexpr (HAS3 && WMAX == 4) {
+      if (ps.w == 3) store<3, S>(buf, ps.ca, ps.cb, ps.z, ps.zi);
+      else store<4, S>(buf, ps.ca, ps.cb, ps.z, ps.zi);
+    } else store<WMAX, S>(buf, ps.ca, ps.cb, ps.z, ps.zi);
   }
 
   template <int P>
   __device__ __forceinline__ void mma_any(int buf, int w) {
     if (w == 2) mma<2, P>(buf);
     else if (w == 1) mma<1, P>(buf);
-    else mma<WMAX, P>(buf);
+    else if constexpr (HAS3 && WMAX == 4) {
+      if (w == 3) mma<3, P>(buf);
+      else mma<4, P>(buf);
+    } else mma<WMAX, P>(buf);
   }
 
   template <int P>
   __device__ __forceinline__ void finish_any(const PairState &ps) {
     if (ps.w == 2) finish<2, P>(ps.inv, ps.z, ps.zi);
     else if (ps.w == 1) finish<1, P>(ps.inv, ps.z, ps.zi);
-    else finish<WMAX, P>(ps.inv, ps.z, ps.zi);
+    else if constexpr (HAS3 && WMAX == 4) {
+      if (ps.w == 3) finish<3, P>(ps.inv, ps.z, ps.zi);
+      else finish<4, P>(ps.inv, ps.z, ps.zi);
+    } else finish<WMAX, P>(ps.inv, ps.z, ps.zi);
   }
 
   // Chunk g of the pair in accumulator set P: compand + pack register set S
@@ -476,12 +502,12 @@ struct Fused {
   }
 };
 
-template <typename IT, typename PT, int L, int FORM, bool TA, bool TB>
+template <typename IT, typename PT, int L, int FORM, bool TA, bool TB, bool K48>
 __global__ __launch_bounds__(4 * L, (L == 64 ? 2 : 1)) void k_fused(GemmOperands g, const IT *__restrict__ A,
                                                  const IT *__restrict__ B, PT *__restrict__ C,
                                                  PT *__restrict__ part, int64_t ntiles,
                                                  int64_t ngroups, int64_t per_xcd) {
-  typedef Fused<IT, PT, L, FORM, TA, TB> F;
+  typedef Fused<IT, PT, L, FORM, TA, TB, K48> F;
   __shared__ typename F::Smem sm;
   // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin, so give
   // each XCD a contiguous range. Groups of the l-sum are the slowest index, so
@@ -531,10 +557,10 @@ __global__ __launch_bounds__(256) void k_sum_groups(const PT *__restrict__ part,
 }
 
 // ---------------------------------------------------------------------------
-template <typename IT, typename PT, int L, int FORM>
+template <typename IT, typename PT, int L, int FORM, bool K48>
 static hipError_t launch_fused_t(const GemmOperands &g, const void *A, const void *B, void *C,
                                  void *part, hipStream_t st) {
-  typedef Fused<IT, PT, L, FORM, false, false> F0;
+  typedef Fused<IT, PT, L, FORM, false, false, K48> F0;
   const int64_t ntiles = g.pb.nI * g.pb.nJ * (L / F0::TN);
   const int64_t ngroups = (g.pb.nL + g.gsize - 1) / g.gsize;
   const int64_t per_xcd = (ntiles * ngroups + 7) / 8;
@@ -545,13 +571,13 @@ static hipError_t launch_fused_t(const GemmOperands &g, const void *A, const voi
   PT *c = (PT *)C;
   PT *p = (PT *)part;
   if (!g.ta && !g.tb)
-    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, false, false>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
+    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, false, false, K48>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
   else if (g.ta && !g.tb)
-    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, true, false>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
+    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, true, false, K48>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
   else if (!g.ta && g.tb)
-    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, false, true>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
+    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, false, true, K48>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
   else
-    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, true, true>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
+    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, true, true, K48>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
   if (ngroups > 1) {
     const int64_t n = g.pb.M * g.pb.N;
     hipLaunchKernelGGL((k_sum_groups<PT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, ngroups,
@@ -565,8 +591,13 @@ static hipError_t launch_fused_t(const GemmOperands &g, const void *A, const voi
 template <typename IT, typename PT, int L>
 hipError_t launch_fused_il(const GemmOperands &g, const void *A, const void *B, void *C, void *part,
                            hipStream_t st) {
-  return g.form == TDGEMM_SYM ? launch_fused_t<IT, PT, L, TDGEMM_SYM>(g, A, B, C, part, st)
-                              : launch_fused_t<IT, PT, L, TDGEMM_ASYM>(g, A, B, C, part, st);
+  if constexpr (L == 96) {
+    if (g.wmax == 4)                        // 48-column chunks: W in {1, 2, 3, 4}
+      return g.form == TDGEMM_SYM ? launch_fused_t<IT, PT, L, TDGEMM_SYM, true>(g, A, B, C, part, st)
+                                  : launch_fused_t<IT, PT, L, TDGEMM_ASYM, true>(g, A, B, C, part, st);
+  }
+  return g.form == TDGEMM_SYM ? launch_fused_t<IT, PT, L, TDGEMM_SYM, false>(g, A, B, C, part, st)
+                              : launch_fused_t<IT, PT, L, TDGEMM_ASYM, false>(g, A, B, C, part, st);
 }
 
 #define TDG_FUSED_INSTANCE(IT, PT, L)                                                         \

@@ -33,7 +33,7 @@ struct PlanLaunch {
   int n_r;
   int ctrl;
   int n_opt;
-  int w_desc[3];
+  int w_desc[4];
   int fixed_w;
   int block_scaled;                    // INT8 / FP8 form: separable records with W = 1
   double fixed_rmax, sep_q, u_safe, snr_lin;
@@ -52,6 +52,7 @@ struct GemmOperands {
   bool ta, tb;
   const tdgemm_pair *pairs;   // [n_pairs]
   int64_t gsize;              // subblocks per group of the l-sum (nL: one group)
+  int wmax;                   // largest packing the plan may hold
 };
 
 hipError_t launch_stats(const StatsArgs &a, int dtype, int L, hipStream_t st);

@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kThreads) void k_stats(StatsArgs a) {
 // exactly rounded sum is within the budget -- is found by bisection over t
 // from the entries' ranks. Otherwise the greedy runs step by step.
 constexpr int kMaxT = 8;          // up to 512 subblocks along K
-constexpr int kMaxOpt = 3;        // allowed W levels: at most {4, 2, 1} or {3, 2, 1}
+constexpr int kMaxOpt = 4;        // allowed W levels: at most {4, 3, 2, 1} (L = 96)
 
 struct PlanArgs {
   Problem pb;

@@ -100,18 +100,23 @@ __global__ __launch_bounds__(kThreads) void k_packed_product(GemmOperands g, con
   const PT *pb = pB + pair * L * L;
   PT *out = Rbar + pair * L * L;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int nrb = rows / 16, ncb = L / 16;
+  // row blocks of 16 (the last one partial when L / W is not a multiple of 16:
+  // asymmetric W = 4 at L = 96); rows past the packed ones read 0 and are not written
+  const int nrb = (rows + 15) / 16, ncb = L / 16;
   for (int blk = wave; blk < nrb * ncb; blk += kThreads / kWave) {
     const int rb = blk / ncb, cb = blk - (blk / ncb) * ncb;
+    const int arow = rb * 16 + (lane & 15);
     typename Mfma<PT>::Acc acc = Mfma<PT>::zero();
     for (int ks = 0; ks < kd / 4; ++ks) {
-      const PT av = pa[(rb * 16 + (lane & 15)) * kd + ks * 4 + (lane >> 4)];
+      const PT av = arow < rows ? pa[arow * kd + ks * 4 + (lane >> 4)] : (PT)0;
       const PT bv = pb[(ks * 4 + (lane >> 4)) * L + cb * 16 + (lane & 15)];
       acc = Mfma<PT>::mma(av, bv, acc);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      out[(rb * 16 + Mfma<PT>::row(lane, r)) * L + cb * 16 + (lane & 15)] = acc[r];
+    for (int r = 0; r < 4; ++r) {
+      const int row = rb * 16 + Mfma<PT>::row(lane, r);
+      if (row < rows) out[row * L + cb * 16 + (lane & 15)] = acc[r];
+    }
   }
 }
 

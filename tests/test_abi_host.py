@@ -92,13 +92,14 @@ def _desc(binding, **kw):
 
 @pytest.mark.parametrize("kw,status", [
     ({}, 0),
-    ({"L": 96}, -2), ({"L": 96, "w_allowed": 2 | 4 | 8}, 0), ({"L": 80}, -2), ({"L": 0}, -1),
+    ({"L": 96}, 0), ({"L": 96, "w_allowed": 2 | 4 | 8}, 0), ({"L": 96, "w_allowed": 2 | 4 | 8 | 16}, 0),
+    ({"L": 80}, -2), ({"L": 0}, -1), ({"L": 128, "w_allowed": 2 | 8}, -1),
     ({"form": 3}, -1), ({"prec": 7}, -1),
     ({"in_dtype": 0, "prec": 1}, -2), ({"M": -1}, -1), ({"lda": 100}, -1), ({"ldc": 10}, -1),
     ({"trans_a": 2}, -1), ({"w_allowed": 4}, -1), ({"w_allowed": 2 | 8}, -1),
     ({"w_allowed": 2 | 32}, -1), ({"ctrl": 9}, -1), ({"snr_db": math.nan}, -1),
     ({"ctrl": 1, "fixed_w": 3}, -1), ({"ctrl": 1, "fixed_w": 3, "L": 96}, 0),
-    ({"ctrl": 1, "fixed_w": 4, "L": 96}, -2), ({"ctrl": 2, "fixed_w": 3, "L": 96}, 0),
+    ({"ctrl": 1, "fixed_w": 4, "L": 96}, 0), ({"ctrl": 2, "fixed_w": 3, "L": 96}, 0),
     ({"ctrl": 1, "fixed_w": 5}, -1), ({"ctrl": 1, "fixed_rmax": 0.0}, -1),
     ({"ctrl": 2, "sep_q": 0.5}, -1), ({"u_safe": 0.0}, -1), ({"K": 64 * 513, "lda": 64 * 513}, -2),
     ({"ctrl": 4}, 0), ({"ctrl": 4, "snr_db": -math.inf}, -1), ({"ctrl": 4, "fixed_rmax": -1.0}, -1),
@@ -174,7 +175,8 @@ def test_calibrate_argument_errors(binding, lib):
     assert f(64, 2, 1, 0, q, 1, z, z, 5, ctypes.c_double(50.0), out, out, out, z, ctypes.c_size_t(1 << 30), None) == -1
     q[0] = 4.0
     assert f(64, 3, 1, 0, q, 1, z, z, 5, ctypes.c_double(50.0), out, out, out, z, ctypes.c_size_t(1 << 30), None) == -1
-    assert f(96, 4, 1, 0, q, 1, z, z, 5, ctypes.c_double(50.0), out, out, out, z, ctypes.c_size_t(1 << 30), None) == -2
+    # W = 4 at L = 96 is a valid packing: the (too small) workspace is what fails
+    assert f(96, 4, 1, 0, q, 1, z, z, 5, ctypes.c_double(50.0), out, out, out, z, ctypes.c_size_t(16), None) == -3
     assert f(80, 2, 1, 0, q, 1, z, z, 5, ctypes.c_double(50.0), out, out, out, z, ctypes.c_size_t(1 << 30), None) == -2
     assert f(64, 2, 1, 0, q, 1, z, z, 5, ctypes.c_double(50.0), out, out, out, z, ctypes.c_size_t(16), None) == -3
 

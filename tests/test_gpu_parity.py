@@ -12,7 +12,7 @@ Bar (integer and byte work bit-exact; floating point within the stated bound):
   oracle with the same grouping bit for bit, and the oracle's plain ascending
   sum within 1e-12 / 1e-5 of |A||B| element by element.
 Shapes span several tiles and ragged tails on every axis; both packing forms,
-all three block sizes (L = 96 with W = 3), all three control modes, transposed operands and the empty
+all three block sizes (L = 96 with W in {1, 2, 3, 4}), all control modes, transposed operands and the empty
 and single-row cases are covered.
 """
 import math
@@ -83,6 +83,14 @@ CASES = [
     ("L96_f32_pack_sym", 200, 300, 100, 96, "sym", "f32", "f32", "snr", 15.0, (1, 2), 2, 0, 0),
     ("L96_f32_pack_asym", 200, 300, 100, 96, "asym", "f32", "f32", "snr", 10.0, (1, 2), 2, 0, 0),
     ("L96_separable_w3", 192, 192, 192, 96, "sym", "f64", "f64", "separable", 0.0, (1, 3), 3, 0, 0),
+    # L = 96 with the whole double-precision set {1, 2, 3, 4} (48-column chunks)
+    ("L96_sym_fixed_w4", 200, 288, 200, 96, "sym", "f64", "f64", "fixed", 0.0, (1, 4), 4, 0, 0),
+    ("L96_asym_fixed_w4", 200, 288, 200, 96, "asym", "f64", "f64", "fixed", 0.0, (1, 4), 4, 0, 0),
+    ("L96_sym_snr20_w1234", 300, 400, 260, 96, "sym", "f64", "f64", "snr", 20.0, (1, 2, 3, 4), 2, 0, 0),
+    ("L96_asym_snr20_w1234", 300, 400, 260, 96, "asym", "f64", "f64", "snr", 20.0, (1, 2, 3, 4), 2, 0, 0),
+    ("L96_asym_snr35_w1234_tab", 150, 200, 90, 96, "asym", "f64", "f64", "snr", 35.0, (1, 2, 3, 4), 2, 1, 1),
+    ("L96_sym_f32_in_w1234_ta", 190, 330, 170, 96, "sym", "f32", "f64", "snr", 25.0, (1, 2, 3, 4), 2, 1, 0),
+    ("L96_target_w4", 192, 288, 200, 96, "asym", "f64", "f64", "target", 10.0, (1, 4), 4, 0, 0),
 ]
 
 
@@ -108,6 +116,8 @@ def test_stagewise_parity(td, case):
     rmax = float(2 ** 20) if L == 64 else float(2 ** 21)
     if fw == 3:
         rmax = float(2 ** 14)            # three 16-bit slots: inside the FP64 mantissa
+    if fw == 4:
+        rmax = float(2 ** 9)             # four 12-bit slots
     calib, tabs = device_calib(td, L, form, prec, tuple(w for w in wal if w > 1) or (2,))
     cfg = oracle_cfg(L, form, prec, ctrl, snr, wal, fw, rmax, 127.0)
     res = pl.run(A, B, cfg, calib=tabs, keep=True)
@@ -209,7 +219,8 @@ def test_empty_shapes(td, M, K, N):
 @pytest.mark.parametrize("form,prec,W,L", [("sym", "f64", 2, 64), ("asym", "f64", 2, 64),
                                            ("sym", "f64", 4, 64), ("sym", "f32", 2, 64),
                                            ("asym", "f64", 2, 128), ("sym", "f64", 3, 96),
-                                           ("asym", "f64", 3, 96), ("asym", "f64", 2, 96)])
+                                           ("asym", "f64", 3, 96), ("asym", "f64", 2, 96),
+                                           ("sym", "f64", 4, 96), ("asym", "f64", 4, 96)])
 def test_calibration_parity(td, form, prec, W, L):
     """Sec. 4.B measurement on the GPU path equals the oracle's on the same draws."""
     from oracle import calibration as cal

@@ -32,7 +32,7 @@ def _wmax(L):
 
 
 def _calib(kind, L, form):
-    tabs = tables(L, form, "f64", (2, _wmax(L)))
+    tabs = tables(L, form, "f64", (2, 3, 4) if L == 96 else (2, 4))
     r = tabs[2].r
     if kind == "scaled_w4":          # W = 4 cheaper than W = 2: D need not fall with W
         tabs = {2: tabs[2], 4: ct.CalibTable(r.copy(), tabs[2].s * 0.25)}
@@ -52,6 +52,7 @@ CASES = [
     ("deep_prune_w2_only", 256, 1024, 64, 64, "sym", 80.0, (1, 2), "laplace", "std"),
     ("L96_many_l", 96, 96 * 70, 96, 96, "sym", 30.0, (1, 2, 3), "gauss", "std"),
     ("L96_asym_ragged", 64, 96 * 50 + 17, 70, 96, "asym", 25.0, (1, 2, 3), "laplace", "std"),
+    ("L96_w1234_many_l", 96, 96 * 70, 96, 96, "sym", 22.0, (1, 2, 3, 4), "gauss", "std"),
 ]
 
 
@@ -75,7 +76,7 @@ def test_plan_parity(td, case):
     tabs = _calib(ckind, L, form)
     cfg = oracle_cfg(L, form, "f64", "snr", snr, wal, 2, 1.0, 127.0)
     ref = pl.make_plan(A, B, cfg, calib=tabs)
-    calib = td.DeviceCalib(tabs[2].r, {W: tabs[W].s for W in (2, _wmax(L))})
+    calib = td.DeviceCalib(tabs[2].r, {W: t.s for W, t in tabs.items()})
     Ad, Bd = to_dev(A), to_dev(B)
     desc = td.make_desc(Ad, Bd, L=L, form=form, prec="f64", ctrl="snr", snr_db=snr, w_allowed=wal)
     plan = td.tdgemm_plan(desc, Ad, Bd, calib)
@@ -108,6 +109,7 @@ ACCEL_CASES = [
     ("accel_ties", 128, 384, 128, 64, "sym", 0.5, (1, 2), "tiled"),
     ("accel_L96_w23", 192, 96 * 20, 96, 96, "sym", 0.55, (1, 2, 3), "laplace"),
     ("accel_L96_asym", 96, 96 * 12, 192, 96, "asym", 0.3, (1, 2, 3), "gauss"),
+    ("accel_L96_w1234", 192, 96 * 20, 96, 96, "sym", 0.6, (1, 2, 3, 4), "laplace"),
 ]
 
 
@@ -120,7 +122,7 @@ def test_accel_plan_parity(td, case):
     tabs = _calib("std", L, form)
     cfg = pl.Config(L=L, form=form, prec="f64", ctrl="accel", accel=frac, w_allowed=tuple(wal))
     ref = pl.make_plan(A, B, cfg, calib=tabs)
-    calib = td.DeviceCalib(tabs[2].r, {W: tabs[W].s for W in (2, _wmax(L))})
+    calib = td.DeviceCalib(tabs[2].r, {W: t.s for W, t in tabs.items()})
     Ad, Bd = to_dev(A), to_dev(B)
     desc = td.make_desc(Ad, Bd, L=L, form=form, prec="f64", ctrl="accel", accel=frac, w_allowed=wal)
     plan = td.tdgemm_plan(desc, Ad, Bd, calib)
@@ -165,7 +167,7 @@ def test_tile_target_plan_parity(td, ctrl, L, form):
                     fixed_rmax=float(2 ** 20),
                     tile_targets=tuple(tuple(float(v) for v in row) for row in tmap))
     ref = pl.make_plan(A, B, cfg, calib=tabs)
-    calib = td.DeviceCalib(tabs[2].r, {W: tabs[W].s for W in (2, _wmax(L))})
+    calib = td.DeviceCalib(tabs[2].r, {W: t.s for W, t in tabs.items()})
     Ad, Bd = to_dev(A), to_dev(B)
     desc = td.make_desc(Ad, Bd, L=L, form=form, prec="f64", ctrl=ctrl, snr_db=40.0, w_allowed=wal,
                         fixed_w=2, fixed_rmax=float(2 ** 20), tile_target=tmap)
@@ -217,7 +219,7 @@ def test_plan_query_vs_oracle(td, case):
                     fixed_rmax=rmax,
                     tile_targets=None if tmap is None else tuple(tuple(float(v) for v in r) for r in tmap))
     ref = pl.make_plan(A, B, cfg, calib=tabs)
-    calib = td.DeviceCalib(tabs[2].r, {W: tabs[W].s for W in (2, _wmax(L))})
+    calib = td.DeviceCalib(tabs[2].r, {W: t.s for W, t in tabs.items()})
     Ad, Bd = to_dev(A), to_dev(B)
     desc = td.make_desc(Ad, Bd, L=L, form=form, prec="f64", ctrl=ctrl, snr_db=snr, w_allowed=wal,
                         fixed_w=fw, fixed_rmax=rmax, tile_target=tmap)
