@@ -320,14 +320,15 @@ def run_sweep_table(args):
         Bd = torch.from_numpy(B).cuda()
         ref = torch.matmul(Ad, Bd)
         C = torch.empty((n, n), dtype=torch.float64, device="cuda")
-        for L in (64, 96, 128):
-            wmax = 3 if L == 96 else 4                   # packings a block size supports
+        # packings a block size supports; L = 96 also with the whole set {1, 2, 3, 4} of Sec. 7
+        for L, wset in ((64, (1, 2, 4)), (96, (1, 2, 3)), (96, (1, 2, 3, 4)), (128, (1, 2, 4))):
             for form in ("sym", "asym"):
                 if (L, form) not in calibs:
-                    calibs[(L, form)] = calibrate_gpu(td, torch, L, form, "f64", [2, wmax])[0]
+                    calibs[(L, form)] = calibrate_gpu(td, torch, L, form, "f64",
+                                                      [2, 3, 4] if L == 96 else [2, 4])[0]
                 calib = calibs[(L, form)]
                 for S in (60.0, 52.0, 44.0, 36.0, 28.0, 20.0):
-                    desc = td.make_desc(Ad, Bd, L=L, form=form, ctrl="snr", snr_db=S, w_allowed=(1, 2, wmax))
+                    desc = td.make_desc(Ad, Bd, L=L, form=form, ctrl="snr", snr_db=S, w_allowed=wset)
                     ws = torch.empty(td.tdgemm_workspace_size(desc), dtype=torch.uint8, device="cuda")
                     holder = {}
 
@@ -341,12 +342,13 @@ def run_sweep_table(args):
 
                     ms, _ = timed_steps(torch, step, 2, max(5, args.steps // 2), 1)
                     _, _, pairs, _ = td.tdgemm_plan_export(holder["plan"])
-                    wh = {int(w): int((pairs["w"] == w).sum()) for w in (1, 2, wmax)}
+                    wh = {int(w): int((pairs["w"] == w).sum()) for w in wset}
                     snr = snr_of(torch, C, ref)
-                    rows.append({"dist": dist, "L": L, "form": form, "snr_target_db": S, "ms": round(ms, 4),
+                    rows.append({"dist": dist, "L": L, "w_allowed": list(wset), "form": form,
+                                 "snr_target_db": S, "ms": round(ms, 4),
                                  "gflops": round(flops / ms / 1e6, 1), "snr_db": round(snr, 2),
                                  "w_histogram": wh})
-                    log(f"[bench] {dist:8s} L={L:3d} {form:4s} S={S:4.0f}: {ms:7.3f} ms "
+                    log(f"[bench] {dist:8s} L={L:3d} W<={max(wset)} {form:4s} S={S:4.0f}: {ms:7.3f} ms "
                         f"{flops / ms / 1e6:9.1f} GFLOP/s  SNR {snr:6.2f} dB  W {wh}")
                     del ws
         plain = time_plain(torch, Ad, Bd, ref)

@@ -9,9 +9,10 @@ C = A B with A (M x K) and B (K x N), following the paper's flow:
 3. per pair: compand (eq. 3), pack (eqs. 6-7 or 11), packed product (eq. 8
    or 12), unpack (eqs. 9-10 or 13-14)                 -> ``packing``
 4. reverse companding (eq. 5) and the l-sum of eq. (2), l ascending:
-   C_ij = C_ij + r * inv for each pair (W = 1 pairs add their native product);
-   with k_groups > 1 the sum runs per group of consecutive l and the group
-   sums are added in ascending order (eq. 2 fixes the sum, not its order).
+   C_ij = fma(r, inv, C_ij) for each pair, one rounding per pair (W = 1 pairs
+   add their native product, i.e. inv = 1) -- an FMA chain over l; with
+   k_groups > 1 the chain runs per group of consecutive l and the group sums
+   are added in ascending order (eqs. 2 and 5 fix the sum, not its roundings).
 
 Control modes:
 * 'snr'        Sec. 5.B / Sec. 6 distortion control with a calibrated s(R, W).
@@ -35,6 +36,7 @@ import numpy as np
 from . import blocks as bk
 from . import control as ct
 from . import packing as pk
+from .fmachain import fma_matmul
 
 
 @dataclass(frozen=True)
@@ -159,7 +161,8 @@ class Result:
 
 def pair_product(a: np.ndarray, b: np.ndarray, opt: ct.PairOption, cfg: Config,
                  keep: bool = False):
-    """Step 3 for one pair: returns (contribution r * inv, trace or None)."""
+    """Step 3 for one pair: returns (r, inv, trace or None), whose contribution
+    to C is r * inv (step 4); W = 1 gives the native product and inv = 1."""
     prec = cfg.prec
     dt = pk.DTYPES[prec]
     if opt.W == 1:
@@ -167,7 +170,7 @@ def pair_product(a: np.ndarray, b: np.ndarray, opt: ct.PairOption, cfg: Config,
         b_ = np.asarray(b, dtype=dt)
         r = pk.packed_product(a_, b_, prec)
         tr = PairTrace(a_, b_, a_, b_, r, r, None) if keep else None
-        return r, tr
+        return r, dt(1.0), tr
     qa = pk.compand(a, opt.c_a, prec)
     qb = pk.compand(b, opt.c_b, prec)
     if cfg.form == "sym":
@@ -182,12 +185,23 @@ def pair_product(a: np.ndarray, b: np.ndarray, opt: ct.PairOption, cfg: Config,
         r = pk.unpack_asym(rbar, opt.W, opt.p, prec)
     else:
         raise ValueError(cfg.form)
-    contrib = pk.decompand(r, opt.inv, prec)
     tr = None
     if keep:
         r_exact = qa.astype(np.int64) @ qb.astype(np.int64)
         tr = PairTrace(qa, qb, abar, bbar, rbar, r, r_exact)
-    return contrib, tr
+    return np.asarray(r, dtype=dt), dt(opt.inv), tr
+
+
+def fma_chain_sum(rs: list, invs: list, prec: str) -> np.ndarray:
+    """Per output, acc = 0; for each pair in order: acc = fma(r, inv, acc) in prec,
+    each step one correctly rounded fused multiply-add: the FMA-chain product of
+    the row (r_0, r_1, ...) by the column (inv_0, inv_1, ...)."""
+    L0, L1 = rs[0].shape
+    n = len(rs)
+    rows = np.ascontiguousarray(np.stack(rs).reshape(n, L0 * L1).T).reshape(L0 * L1, 1, n)
+    cols = np.ascontiguousarray(np.broadcast_to(np.asarray(invs, dtype=rows.dtype).reshape(1, n, 1),
+                                                (L0 * L1, n, 1)))
+    return fma_matmul(rows, cols, prec).reshape(L0, L1)
 
 
 def group_size(nl: int, k_groups: int) -> int:
@@ -214,14 +228,16 @@ def run(A: np.ndarray, B: np.ndarray, cfg: Config, calib: dict | None = None,
     for (i, j) in tiles:
         total = np.zeros((L, L), dtype=dt)
         for l0 in range(0, nL, size):
-            acc = np.zeros((L, L), dtype=dt)
+            rs, invs = [], []
             for l in range(l0, min(l0 + size, nL)):
                 a = bk.block(A, i, l, L)
                 b = bk.block(B, l, j, L)
-                contrib, tr = pair_product(a, b, plan.chosen[(i, j, l)], cfg, keep)
-                acc = (acc + contrib).astype(dt)
+                r, inv, tr = pair_product(a, b, plan.chosen[(i, j, l)], cfg, keep)
+                rs.append(r)
+                invs.append(inv)
                 if keep:
                     res.traces[(i, j, l)] = tr
+            acc = fma_chain_sum(rs, invs, cfg.prec)
             total = (total + acc).astype(dt)
         rows = min(L, M - i * L)
         cols = min(L, N - j * L)

@@ -12,7 +12,7 @@
 // the tile, accumulating the packed product over the packed index in ascending
 // order. After a pair's last chunk the packed result is unpacked in registers
 // (eqs. 9-10 or 13-14), reverse-companded (eq. 5) and added to a
-// register-resident C tile (eq. 2). W = 1 pairs run the plain product. C (or
+// register-resident C tile (eq. 2), C = fma(r, inv, C): one rounding per pair. W = 1 pairs run the plain product. C (or
 // the group's partial result) is written once at the end.
 //
 // Row placement: lane (g = lane / 16, c = lane % 16) keeps, for its row block
@@ -320,7 +320,7 @@ struct Fused {
             const PT u = rint(accR[P][a][b][r]);
             const PT t = rint(z * u);
             const PT rr = __builtin_fma(-zi, t, u);     // exact: zi * t is a power-of-two multiple
-            accC[a][b][r] = accC[a][b][r] + rr * inv;
+            accC[a][b][r] = __builtin_fma(rr, inv, accC[a][b][r]);
           }
       } else if (L96) {                          // eqs. (13)-(14): W rows per word
         // word k = 4 a + r of a lane group (k < 24 / W) yields its rows W k + s,
@@ -335,7 +335,7 @@ struct Fused {
             for (int sl = 0; sl < W; ++sl) {
               const PT q = rint(t);
               const int o = W * (4 * a + r) + sl;
-              accC[o >> 2][b][o & 3] = accC[o >> 2][b][o & 3] + q * inv;
+              accC[o >> 2][b][o & 3] = __builtin_fma(q, inv, accC[o >> 2][b][o & 3]);
               if (sl + 1 < W) t = zi * (t - q);
             }
           }
@@ -348,8 +348,8 @@ struct Fused {
             const PT q0 = rint(v);
             const PT q1 = rint(zi * (v - q0));
             const int ra_ = 2 * a + (r >> 1), rr_ = (r & 1) * 2;
-            accC[ra_][b][rr_] = accC[ra_][b][rr_] + q0 * inv;
-            accC[ra_][b][rr_ + 1] = accC[ra_][b][rr_ + 1] + q1 * inv;
+            accC[ra_][b][rr_] = __builtin_fma(q0, inv, accC[ra_][b][rr_]);
+            accC[ra_][b][rr_ + 1] = __builtin_fma(q1, inv, accC[ra_][b][rr_ + 1]);
           }
       } else {                                   // W == 4: four rows per word
 #pragma unroll
@@ -364,10 +364,10 @@ struct Fused {
             const PT q2 = rint(t2);
             const PT q3 = rint(zi * (t2 - q2));
             const int ra_ = 4 * a + r;
-            accC[ra_][b][0] = accC[ra_][b][0] + q0 * inv;
-            accC[ra_][b][1] = accC[ra_][b][1] + q1 * inv;
-            accC[ra_][b][2] = accC[ra_][b][2] + q2 * inv;
-            accC[ra_][b][3] = accC[ra_][b][3] + q3 * inv;
+            accC[ra_][b][0] = __builtin_fma(q0, inv, accC[ra_][b][0]);
+            accC[ra_][b][1] = __builtin_fma(q1, inv, accC[ra_][b][1]);
+            accC[ra_][b][2] = __builtin_fma(q2, inv, accC[ra_][b][2]);
+            accC[ra_][b][3] = __builtin_fma(q3, inv, accC[ra_][b][3]);
           }
       }
     }

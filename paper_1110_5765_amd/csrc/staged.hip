@@ -154,9 +154,9 @@ __global__ __launch_bounds__(kThreads) void k_unpack_pairs(GemmOperands g, const
   }
 }
 
-// Eq. (5) and the l-sum of eq. (2): C = sum_l r_l * inv_l, l ascending, in
-// groups of gsize consecutive l (each from zero), the group sums added in
-// ascending order to zero.
+// Eq. (5) and the l-sum of eq. (2): C = fma(r_l, inv_l, C), l ascending (one
+// rounding per pair; W = 1 pairs add their native product), in groups of gsize
+// consecutive l (each from zero), the group sums added in ascending order to zero.
 template <typename PT>
 __global__ __launch_bounds__(kThreads) void k_decompand_sum(GemmOperands g, const PT *Rbar, PT *C) {
   const Problem &pb = g.pb;
@@ -175,8 +175,7 @@ __global__ __launch_bounds__(kThreads) void k_decompand_sum(GemmOperands g, cons
     const int64_t pair = (i * pb.nJ + j) * pb.nL + l;
     const tdgemm_pair o = g.pairs[pair];
     const PT r = unpack_one<PT>(Rbar + pair * L * L, m, n, L, o, g.form);
-    const PT contrib = (o.w == 1) ? r : r * (PT)o.inv;
-    acc = acc + contrib;
+    acc = (o.w == 1) ? acc + r : __builtin_fma(r, (PT)o.inv, acc);
     if ((l + 1) % g.gsize == 0 || l + 1 == pb.nL) {
       sum = sum + acc;
       acc = (PT)0;

@@ -164,3 +164,41 @@ def test_remark2_storage(W, L):
     asym_words = pk.pack_asym_a(qa, W, 10, "f64").size + qa.size
     assert sym_words == 2 * L * L // W
     assert asym_words == L * L + L * L // W
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_lsum_is_one_fused_multiply_add_per_pair(prec):
+    """Eqs. (5) and (2): C = fma(r, 1/(c_A c_B), C) for l ascending from 0, one
+    rounding per pair in the packing precision (W = 1 pairs add their native
+    product) -- checked against exact rational arithmetic on sampled outputs,
+    on a case where multiply-then-add would round differently somewhere."""
+    from fractions import Fraction
+
+    from oracle import pipeline as pl
+    from tests.oracle_tables import tables
+    from tests.test_oracle_precision import _round_f32
+    rng = np.random.default_rng(5 if prec == "f64" else 6)
+    L, nl = 64, 5
+    A = rng.standard_normal((L, nl * L)) * rng.uniform(0.5, 4.0, (1, nl * L))
+    B = rng.laplace(0.0, 1.0, (nl * L, L))
+    if prec == "f32":
+        A, B = A.astype(np.float32), B.astype(np.float32)
+    cfg = pl.Config(L=L, form="sym", prec=prec, ctrl="snr", snr_db=30.0 if prec == "f64" else 12.0,
+                    w_allowed=(1, 2))
+    res = pl.run(A, B, cfg, calib=tables(L, "sym", prec, (2,)), keep=True)
+    rnd = (lambda x: float(x)) if prec == "f64" else _round_f32
+    dt = np.float64 if prec == "f64" else np.float32
+    ws = [res.plan.chosen[(0, 0, l)].W for l in range(nl)]
+    assert 2 in ws
+    differs = 0
+    for (m, n) in [(int(a), int(b)) for a, b in rng.integers(0, L, (60, 2))]:
+        acc, naive = Fraction(0), dt(0.0)
+        for l in range(nl):
+            o = res.plan.chosen[(0, 0, l)]
+            r = res.traces[(0, 0, l)].r[m, n]
+            inv = 1.0 if o.W == 1 else float(dt(o.inv))
+            acc = Fraction(rnd(Fraction(float(r)) * Fraction(inv) + acc))
+            naive = naive + (dt(r) if o.W == 1 else dt(r) * dt(o.inv))
+        assert res.C[m, n] == dt(float(acc)), (m, n)
+        differs += int(dt(float(acc)) != naive)
+    assert differs > 0
