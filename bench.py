@@ -783,7 +783,7 @@ def run_pca2d(args):
     def gemm(A, B, snr, ws_cache):
         if snr is None:
             return torch.matmul(A, B)
-        ks = td.auto_k_split(A.shape[0], B.shape[1], A.shape[1], L) if args.k_split else 1
+        ks = td.auto_k_split(A.shape[0], B.shape[1], A.shape[1], L, "f32") if args.k_split else 1
         desc = td.make_desc(A, B, L=L, form=args.form, prec="f32", ctrl="snr", snr_db=snr, w_allowed=(1, 2),
                             k_split=ks)
         key = (A.shape, B.shape, A.stride(), B.stride(), ks)
@@ -878,7 +878,7 @@ def run_scatter(args):
         ref = torch.matmul(A.double(), B.double())
         res[name] = {"M": M, "N": N, "K": K}
         for S in (50.0, 40.0, 20.0):
-            ks = td.auto_k_split(M, N, K, L) if args.k_split else 1
+            ks = td.auto_k_split(M, N, K, L, "f64") if args.k_split else 1
             desc = td.make_desc(A, B, L=L, form=args.form, prec="f64", ctrl="snr", snr_db=S,
                                 w_allowed=(1, 2, 4), k_split=ks)
             ws = torch.empty(td.tdgemm_workspace_size(desc), dtype=torch.uint8, device="cuda")

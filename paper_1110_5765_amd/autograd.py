@@ -63,7 +63,7 @@ class TDContext:
         if min(M, N, K) < c.min_dim:
             self.plain_calls += 1
             return A @ B
-        ks = td.auto_k_split(M, N, K, c.L) if c.k_split is None else c.k_split
+        ks = td.auto_k_split(M, N, K, c.L, c.prec) if c.k_split is None else c.k_split
         desc = td.make_desc(A, B, L=c.L, form=c.form, prec=c.prec, ctrl=c.ctrl, snr_db=c.snr_db,
                             w_allowed=c.w_allowed, fixed_w=c.fixed_w, fixed_rmax=c.fixed_rmax,
                             sep_q=c.sep_q, k_split=ks)

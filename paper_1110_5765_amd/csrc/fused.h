@@ -1,19 +1,21 @@
 // Fused throughput-distortion GEMM: every stage of a subblock pair in one
 // kernel (Sec. 3 with the settings of Sec. 5.B / Sec. 6).
 //
-// A workgroup computes an L x TN slab of one inner kernel R_ij (TN = 64 at
-// L = 64 and 128, 96 at L = 96) and walks its pairs l in ascending order --
-// all of them, or one group of consecutive l when the l-sum is split (the
-// group sums are then added in order by k_sum_groups). Each pair's K extent is
-// cut into chunks of KC raw columns (16, 24 or 32). For every chunk the threads
-// load raw A / B values from HBM one or two chunks ahead, compand them (eq. 3)
-// and pack them (eqs. 6-7, or 11) into a double-buffered LDS tile; each
-// wavefront then runs FP64 (or FP32) 16x16x4 MFMAs for its 16 RB x 16 part of
-// the tile, accumulating the packed product over the packed index in ascending
-// order. After a pair's last chunk the packed result is unpacked in registers
-// (eqs. 9-10 or 13-14), reverse-companded (eq. 5) and added to a
-// register-resident C tile (eq. 2), C = fma(r, inv, C): one rounding per pair. W = 1 pairs run the plain product. C (or
-// the group's partial result) is written once at the end.
+// A workgroup computes an L x TN slab of one inner kernel R_ij (the whole
+// inner kernel, TN = L, but for FP32 packing at L = 128: TN = 64) and walks its pairs
+// l in ascending order -- all of them, or one group of consecutive l when the
+// l-sum is split (the group sums are then added in order by k_sum_groups).
+// Each pair's K
+// extent is cut into chunks of KC raw columns (16, 24 or 48). For every chunk
+// the threads load raw A / B values from HBM one or two chunks ahead, compand
+// them (eq. 3) and pack them (eqs. 6-7, or 11) into a double-buffered LDS
+// tile; each wavefront then runs FP64 (or FP32) 16x16x4 MFMAs for its
+// 16 RB x 16 CB part of the tile, accumulating the packed product over the
+// packed index in ascending order. After a pair's last chunk the packed
+// result is unpacked in registers (eqs. 9-10 or 13-14), reverse-companded
+// (eq. 5) and added to a register-resident C tile (eq. 2) as
+// C = fma(r, inv, C), one rounding per pair. W = 1 pairs run the plain
+// product. C (or the group's partial result) is written once at the end.
 //
 // Row placement: lane (g = lane / 16, c = lane % 16) keeps, for its row block
 // a and register r, the C element of tile row 16 a + 4 g + r of its wavefront
@@ -85,20 +87,24 @@ template <typename IT, typename PT, int L, int FORM, bool TA, bool TB, bool K48 
 struct Fused {
   static constexpr bool L96 = L == 96;
   static_assert(!K48 || L96, "48-column chunks are the L = 96 variant with W = 4");
-  static constexpr int TN = L96 ? 96 : 64;  // output columns per workgroup
+  // L = 128, FP64 packing: one workgroup per inner kernel (128 x 128), so each
+  // subblock of A and B is companded and packed once per inner kernel. FP32
+  // packing keeps two 128 x 64 slabs per inner kernel.
+  static constexpr bool WIDE = L == 128 && sizeof(PT) == 8;
+  static constexpr int TN = L96 ? 96 : (WIDE ? 128 : 64);  // output columns per workgroup
   static constexpr int NT = 4 * L;        // threads: L / 16 wavefronts
-  static constexpr int WC = L96 ? 6 : 4;  // wavefront columns, 16 output columns each
+  static constexpr int WC = L96 ? 6 : 4;  // wavefront columns, 16 CB output columns each
   static constexpr int RB = L96 ? 6 : 4;  // 16-row blocks per wavefront
-  static constexpr int CB = 1;            // 16-column blocks per wavefront
-  static constexpr int KC = (L == 64) ? 16 : (L96 ? (K48 ? 48 : 24) : 32);  // raw inner columns per chunk
+  static constexpr int CB = WIDE ? 2 : 1; // 16-column blocks per wavefront
+  static constexpr int KC = (L == 64 || WIDE) ? 16 : (L96 ? (K48 ? 48 : 24) : 32);  // raw inner columns per chunk
   static constexpr int VA = KC * L / NT;  // raw A values per thread per chunk
   static constexpr int VB = KC * TN / NT; // raw B values per thread per chunk
   static constexpr int WMAX = (L96 && !K48) ? 3 : 4;  // packings: {1, 2, WMAX}, and 3 at L = 96
   static constexpr bool HAS3 = L96;
   // packed accumulator sets: two let a pair's unpack overlap the next pair's
-  // MFMAs; with one (L = 96, six row blocks per wavefront) the unpack runs
-  // before them
-  static constexpr int NACC = L96 ? 1 : 2;
+  // MFMAs (L = 64); with one (L = 96 and 128, six row blocks or two column
+  // blocks per wavefront) a pair is unpacked right after its own MFMAs
+  static constexpr int NACC = (L96 || WIDE) ? 1 : 2;
   // LDS row strides in elements. A 64-bit fragment read serves 32 lanes at a
   // time over 64 four-byte banks: lane groups g = 0, 1 read rows lc = 0..15 at
   // column g (A) or column lc of rows g (B). With SA = KC + 2 (2 mod 32) the 32
@@ -119,9 +125,9 @@ struct Fused {
   static constexpr bool A_QUAD = FORM == TDGEMM_SYM && !TA;
   static constexpr bool A_SPLIT = A_QUAD && VA == 8;
   static constexpr int koffA(int v) { return A_SPLIT ? (v % 4) + 16 * (v / 4) : v; }
-  // register sets of raw loads: the prefetch distance in chunks (one at L = 96,
-  // where the six row blocks per wavefront leave fewer registers)
-  static constexpr int PF = L96 ? 1 : 2;
+  // register sets of raw loads: the prefetch distance in chunks (one at L = 96
+  // and 128, where the larger accumulator tiles leave fewer registers)
+  static constexpr int PF = (L96 || WIDE) ? 1 : 2;
   typedef typename Mfma<PT>::Acc Acc;
   static_assert(VA * NT == KC * L && VB * NT == KC * TN, "loads must cover a chunk");
   static_assert(KC % (4 * WMAX) == 0 && KC % 8 == 0 && (!HAS3 || KC % 12 == 0),
@@ -162,7 +168,7 @@ struct Fused {
     lc = lane & 15;
     wr = (tid >> 6) / WC;
     wrow = wr * 16 * RB;
-    wcol = ((tid >> 6) % WC) * 16;
+    wcol = ((tid >> 6) % WC) * 16 * CB;
     if (FORM == TDGEMM_SYM) {
       // 16 consecutive lanes take 16 consecutive rows, so that their LDS
       // stores hit distinct banks; the 4 lane groups of a wavefront cover the
@@ -423,12 +429,12 @@ struct Fused {
     } else finish<WMAX, P>(ps.inv, ps.z, ps.zi);
   }
 
-  // Chunk g of the pair in accumulator set P: compand + pack register set S
-  // into LDS buffer g % 2, barrier, issue the raw loads of chunk g + PF into
-  // set S (PF chunks of matrix work before they are needed), run chunk g's
-  // MFMAs. In the first chunk of a pair the previous pair is unpacked: with two
-  // accumulator sets right after these MFMAs are issued (set 1 - P; measured
-  // faster than unpacking first), with one before them.
+  // Chunk g of the pair in accumulator set P (two sets): compand + pack
+  // register set S into LDS buffer g % 2, barrier, issue the raw loads of chunk
+  // g + PF into set S (PF chunks of matrix work before they are needed), run
+  // chunk g's MFMAs. In the first chunk of a pair the previous pair, in set
+  // 1 - P, is unpacked right after these MFMAs are issued (measured faster than
+  // unpacking first).
   template <bool CHECK, int S, int P>
   __device__ __forceinline__ void iter(int64_t g, int64_t total, const PairState &ps,
                                        const PairState &prev, bool finish_prev) {
@@ -439,9 +445,8 @@ struct Fused {
     // loads in flight is the same on every path and waits count exactly
     const int64_t g2 = g + PF < total ? g + PF : total - 1;
     load<CHECK, S>((g2 / NCH) * L + (g2 % NCH) * KC);
-    if (NACC == 1 && finish_prev) finish_any<0>(prev);
     mma_any<P>(buf, ps.w);
-    if (NACC == 2 && finish_prev) finish_any<NACC - 1 - P>(prev);
+    if (finish_prev) finish_any<1 - P>(prev);
   }
 
   // All chunks of pair l (NCH is even, so chunk parity restarts with each pair).
@@ -460,11 +465,67 @@ struct Fused {
     }
   }
 
+  // One accumulator set: pair l with its packing W fixed for all of its chunks,
+  // unpacked right after its last MFMAs. Dispatching on W once per pair (not
+  // per stage of a chunk) keeps the register allocation of each W separate;
+  // per stage, the 128 x 128 tile spills.
+  template <bool CHECK, int W>
+  __device__ __forceinline__ void pair_w(int64_t l, int64_t total, const PairState &ps) {
+    const int64_t g0 = l * NCH;
+#pragma unroll 1
+    for (int kc = 0; kc < NCH; kc += 2) {
+      static_for<0, 2>([&](auto hc) {
+        constexpr int h = decltype(hc)::value;   // LDS buffer of chunk g0 + kc + h
+        constexpr int S = PF == 2 ? h : 0;        // register set of its raw values
+        store<W, S>(h, ps.ca, ps.cb, ps.z, ps.zi);
+        lds_barrier();
+        const int64_t g = g0 + kc + h;
+        const int64_t g2 = g + PF < total ? g + PF : total - 1;
+        load<CHECK, S>((g2 / NCH) * L + (g2 % NCH) * KC);
+        mma<W, 0>(h);
+      });
+    }
+    finish<W, 0>(ps.inv, ps.z, ps.zi);
+  }
+
+  template <bool CHECK>
+  __device__ __forceinline__ void pair1(int64_t l, int64_t total, const tdgemm_pair *prs) {
+    const PairState ps = pair_state(prs[l]);
+    if (ps.w == 2) pair_w<CHECK, 2>(l, total, ps);
+    else if (ps.w == 1) pair_w<CHECK, 1>(l, total, ps);
+    else if constexpr (HAS3 && WMAX == 4) {
+      if (ps.w == 3) pair_w<CHECK, 3>(l, total, ps);
+      else pair_w<CHECK, 4>(l, total, ps);
+    } else pair_w<CHECK, WMAX>(l, total, ps);
+  }
+
   // Walk all pairs of the tile. A tile inside M and N needs bounds checks only
   // for chunks that reach past K (chunk g starts at inner index g KC): pairs
   // whose prefetches all stay inside K run unchecked, the rest checked.
   template <bool CHECK>
   __device__ __forceinline__ void run(const tdgemm_pair *prs, int64_t nL) {
+    if constexpr (NACC == 1) run1<CHECK>(prs, nL);
+    else run2<CHECK>(prs, nL);
+  }
+
+  // One accumulator set: pair after pair.
+  template <bool CHECK>
+  __device__ __forceinline__ void run1(const tdgemm_pair *prs, int64_t nL) {
+    const int64_t total = nL * NCH;
+    const int64_t kfull = (pb.K - kb) / KC;                           // chunks inside K
+    const int64_t tail = CHECK ? 0 : (kfull < total ? kfull : total);  // first chunk crossing K
+    if (tail > 0) load<false, 0>(0); else load<true, 0>(0);
+    if (PF == 2 && total > 1) { if (tail > 1) load<false, PF - 1>(KC); else load<true, PF - 1>(KC); }
+    // pair l prefetches up to chunk (l + 1) NCH + PF - 1
+    const int64_t l1 = tail >= PF ? (tail - PF) / NCH : 0;
+    int64_t l = 0;
+    for (; l < l1; ++l) pair1<false>(l, total, prs);
+    for (; l < nL; ++l) pair1<true>(l, total, prs);
+  }
+
+  // Two accumulator sets: pairs in twos, each unpacked during the next one.
+  template <bool CHECK>
+  __device__ __forceinline__ void run2(const tdgemm_pair *prs, int64_t nL) {
     const int64_t total = nL * NCH;
     const int64_t kfull = (pb.K - kb) / KC;                           // chunks inside K
     const int64_t tail = CHECK ? 0 : (kfull < total ? kfull : total);  // first chunk crossing K

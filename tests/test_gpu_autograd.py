@@ -62,7 +62,7 @@ def test_packed_gradients_vs_oracle_and_fp64(ag, snr):
     import dataclasses
 
     def oracle(a, b):      # the library groups the l-sum as auto_k_split says
-        ks = td.auto_k_split(a.shape[0], b.shape[1], a.shape[1], L)
+        ks = td.auto_k_split(a.shape[0], b.shape[1], a.shape[1], L, "f32")
         return pl.run(a, b, dataclasses.replace(ocfg, k_groups=ks), calib=tabs).C
 
     ref = {"Y": oracle(X, W), "dX": oracle(G, W.T.copy()), "dW": oracle(X.T.copy(), G)}

@@ -183,7 +183,7 @@ def test_scatter_full_size(td):
     for name, (A, B, Ad, Bd) in {"XtX": (xs.T, xs, X.t(), X), "XP": (xs, ps, X, P)}.items():
         M, K = A.shape
         N = B.shape[1]
-        ks = td.auto_k_split(M, N, K, L)
+        ks = td.auto_k_split(M, N, K, L, "f64")
         desc = td.make_desc(Ad, Bd, L=L, form="sym", prec="f64", ctrl="snr", snr_db=snr, w_allowed=wal,
                             k_split=ks)
         plan = td.tdgemm_plan(desc, Ad, Bd, calib)
@@ -226,7 +226,7 @@ def test_perceptron_step_products_full_size(td):
         C = tdc.matmul(Ad, Bd)
         torch.cuda.synchronize()
         assert tdc.plain_calls == 0
-        ks = td.auto_k_split(M, N, K, L)
+        ks = td.auto_k_split(M, N, K, L, "f32")
         nI, nJ = -(-M // L), -(-N // L)
         tiles = _sample_tiles(nI, nJ, seed=M + N)
         _check_product(td, f"perceptron {name}", np.ascontiguousarray(A), np.ascontiguousarray(B), Ad, Bd,
@@ -249,7 +249,7 @@ def test_pca2d_full_size(td):
     def lib(Ad, Bd):
         M, K = Ad.shape
         N = Bd.shape[1]
-        ks = td.auto_k_split(M, N, K, L)
+        ks = td.auto_k_split(M, N, K, L, "f32")
         desc = td.make_desc(Ad, Bd, L=L, form="sym", prec="f32", ctrl="snr", snr_db=snr, w_allowed=(1, 2),
                             k_split=ks)
         plan = td.tdgemm_plan(desc, Ad, Bd, calib)

@@ -40,7 +40,7 @@ def test_pca2d_gemms(td, snr):
     cfg = oracle_cfg(L, "sym", "f32", "snr", snr, (1, 2), 2, 1.0, 127.0)
 
     def ks(A, B):
-        return td.auto_k_split(A.shape[0], B.shape[1], A.shape[1], L)
+        return td.auto_k_split(A.shape[0], B.shape[1], A.shape[1], L, "f32")
 
     def lib(A, B):
         desc = td.make_desc(A, B, L=L, form="sym", prec="f32", ctrl="snr", snr_db=snr, w_allowed=(1, 2),
