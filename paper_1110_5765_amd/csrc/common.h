@@ -135,23 +135,53 @@ __device__ __forceinline__ double partials_round(const double *part, int np) {
   return hi;
 }
 
-// Exactly rounded sum of v[0..TT) over the 64 lanes of a wavefront; every lane
-// gets the same value. scr: this wavefront's LDS scratch of at least 64 TT + 64
-// doubles, used only when the compensated sum cannot be certified.
+// Orders this wavefront's LDS accesses around the point of the call.
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A compensated pair that also records whether every addition into c was
+// exact. If so, s + c is the exact sum (each TwoSum error is exact), and
+// rounding it once gives the exactly rounded sum with no certificate: this is
+// the common case of a few terms whose exact sum needs only a few bits beyond
+// s, and it includes exact ties, which the certificate can never decide.
+struct XSum {
+  double s, c;
+  int exact;
+};
+
+__device__ __forceinline__ XSum xsum_add(XSum x, double v) {
+  double s, e, c, ec;
+  two_sum(x.s, v, s, e);
+  two_sum(x.c, e, c, ec);
+  return XSum{s, c, x.exact & (ec == 0.0 ? 1 : 0)};
+}
+
+__device__ __forceinline__ XSum xsum_merge(XSum x, XSum y) {
+  double s, e, c1, e1, c, e2;
+  two_sum(x.s, y.s, s, e);
+  two_sum(x.c, y.c, c1, e1);
+  two_sum(c1, e, c, e2);
+  return XSum{s, c, x.exact & y.exact & ((e1 == 0.0 && e2 == 0.0) ? 1 : 0)};
+}
+
+// Exactly rounded sum of v[0..TT) over the 64 lanes of a wavefront; every lane
+// gets the same value. scr: this wavefront's LDS scratch of at least 64 TT + 64
+// doubles, used only when the compensated sum is neither exact nor certified.
 template <int TT>
 __device__ __forceinline__ double wave_sum_exact(const double (&v)[TT], double *scr) {
   const int lane = threadIdx.x & (kWave - 1);
-  CSum x{0.0, 0.0};
+  XSum x{0.0, 0.0, 1};
 #pragma unroll
-  for (int t = 0; t < TT; ++t) x = csum_add(x, v[t]);
-  x = wave_csum_pair(x);
+  for (int t = 0; t < TT; ++t) x = xsum_add(x, v[t]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+    x = xsum_merge(x, XSum{__shfl_xor(x.s, off), __shfl_xor(x.c, off), __shfl_xor(x.exact, off)});
+  x = XSum{__shfl(x.s, 0), __shfl(x.c, 0), __shfl(x.exact, 0)};
   double r;
+  if (x.exact && isfinite(x.s)) return x.s + x.c;
   if (certified_round(x.s, x.c, (int64_t)kWave * TT, r)) return r;
   wave_sync_lds();
 #pragma unroll
@@ -160,7 +190,8 @@ __device__ __forceinline__ double wave_sum_exact(const double (&v)[TT], double *
   if (lane == 0) {
     double *part = scr + kWave * TT;
     int np = 0;
-    for (int k = 0; k < kWave * TT; ++k) partials_add(part, np, scr[k]);
+    for (int k = 0; k < kWave * TT; ++k)
+      if (scr[k] != 0.0) partials_add(part, np, scr[k]);
     r = partials_round(part, np);
   }
   r = __shfl(r, 0);
