@@ -58,7 +58,7 @@ PEAK_F64_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
 PEAK_F32_TFLOPS = 157.3
 HBM_GBS = 8000.0
 
-FUSED_SOURCES = ["paper_1110_5765_amd/csrc/fused.hip", "paper_1110_5765_amd/csrc/mfma.h",
+FUSED_SOURCES = ["paper_1110_5765_amd/csrc/fused.h", "paper_1110_5765_amd/csrc/mfma.h",
                  "paper_1110_5765_amd/csrc/common.h"]
 
 
