@@ -76,9 +76,8 @@ __device__ __forceinline__ CSum wave_csum_pair(CSum x) {
 // exact_bound() is n^2 2^-100 |s + c|, a generous multiple of that.
 // certified_round() returns r = fl(s + c) and whether r is certainly the
 // exactly rounded S: S then lies strictly inside r's rounding interval. Where
-// it does not, the caller sums the terms again with the partials method of
-// Shewchuk (Adaptive Precision Floating-Point Arithmetic, 1997): exact
-// non-overlapping partials, then one rounding to nearest, ties to even.
+// it does not, the caller sums the terms again exactly in a long accumulator
+// (below) and rounds once to nearest, ties to even.
 __device__ __forceinline__ double exact_bound(int64_t n, double r) {
   return (((double)n * (double)n) * 0x1p-100) * fabs(r);
 }
@@ -95,44 +94,81 @@ __device__ __forceinline__ bool certified_round(double s, double c, int64_t n, d
   return fabs(t) + exact_bound(n, r) < 0.5 * gap;
 }
 
-// Exact partials: part[0..np) non-overlapping, increasing in magnitude, summing
-// exactly to every term added so far. At most 64 partials are ever needed for
-// binary64 (each covers a disjoint range of the 2098 exponent bits).
-constexpr int kMaxPartials = 64;
+// Exact long accumulator: the terms' exact sum as signed 64-bit limbs, limb k
+// holding digits of weight 2^(32 k - 1074), so that every finite double is a
+// whole number of units 2^-1074. A term adds its 53-bit significand, split into
+// three 32-bit pieces, to three limbs with LDS atomics (any order, any number of
+// threads); each limb stays far from overflow for fewer than 2^28 terms.
+// lacc_round() then propagates the carries and rounds once to nearest, ties to
+// even. 68 limbs cover 2176 bits: the 2098 of binary64 plus the carries.
+constexpr int kAccLimbs = 68;
 
-__device__ __forceinline__ void partials_add(double *part, int &np, double x) {
-  int k = 0;
-  for (int j = 0; j < np; ++j) {
-    double y = part[j];
-    if (fabs(x) < fabs(y)) { const double tmp = x; x = y; y = tmp; }
-    const double hi = x + y;                      // |x| >= |y|: hi + lo == x + y exactly
-    const double lo = y - (hi - x);
-    if (lo != 0.0) part[k++] = lo;
-    x = hi;
-  }
-  np = k;
-  if (x != 0.0) part[np++] = x;
+__device__ __forceinline__ void lacc_add(int64_t *acc, double x) {
+  const uint64_t bits = (uint64_t)__double_as_longlong(x);
+  const int ex = (int)((bits >> 52) & 0x7ff);
+  uint64_t m = bits & ((uint64_t(1) << 52) - 1);
+  if (ex != 0) m |= uint64_t(1) << 52;
+  if (m == 0) return;
+  const int b = ex == 0 ? 0 : ex - 1;              // weight of m's unit bit, in units 2^-1074
+  const int k = b >> 5, sh = b & 31;
+  const uint64_t lo = m << sh;                      // bits 0..63 of m 2^sh
+  const uint64_t hi = sh ? (m >> (64 - sh)) : 0;    // bits 64..84
+  const int64_t d0 = (int64_t)(lo & 0xffffffffu), d1 = (int64_t)(lo >> 32), d2 = (int64_t)hi;
+  const bool neg = (bits >> 63) != 0;
+  atomicAdd((unsigned long long *)&acc[k], (unsigned long long)(neg ? -d0 : d0));
+  atomicAdd((unsigned long long *)&acc[k + 1], (unsigned long long)(neg ? -d1 : d1));
+  atomicAdd((unsigned long long *)&acc[k + 2], (unsigned long long)(neg ? -d2 : d2));
 }
 
-// The sum of the partials rounded once to nearest (ties to even).
-__device__ __forceinline__ double partials_round(const double *part, int np) {
-  if (np == 0) return 0.0;
-  int n = np - 1;
-  double hi = part[n], lo = 0.0;
-  while (n > 0) {                                 // add from the top while exact
-    const double x = hi, y = part[--n];
-    hi = x + y;
-    lo = y - (hi - x);
-    if (lo != 0.0) break;
+// One thread: the accumulated sum rounded once to nearest, ties to even. The
+// limbs are normalised in place (digits in [0, 2^32), the magnitude if the sum
+// is negative).
+__device__ inline double lacc_round(int64_t *acc) {
+  int64_t carry = 0;
+  for (int k = 0; k < kAccLimbs; ++k) {
+    const int64_t v = acc[k] + carry;
+    carry = v >> 32;                                // floor division by 2^32
+    acc[k] = v - (carry << 32);
   }
-  // hi + lo is exact but the partials below lo may push the sum past the
-  // half-way point that hi's rounding assumed: then round the other way
-  if (n > 0 && ((lo < 0.0 && part[n - 1] < 0.0) || (lo > 0.0 && part[n - 1] > 0.0))) {
-    const double y = lo * 2.0;
-    const double x = hi + y;
-    if (x - hi == y) hi = x;
+  const bool neg = carry < 0;                       // the sum is carry 2^(32 kAccLimbs) + digits
+  if (neg) {                                        // magnitude: two's complement of the digits
+    int64_t c = 1;
+    for (int k = 0; k < kAccLimbs; ++k) {
+      const int64_t v = (0xffffffffll - acc[k]) + c;
+      c = v >> 32;
+      acc[k] = v & 0xffffffffll;
+    }
   }
-  return hi;
+  int h = kAccLimbs - 1;
+  while (h >= 0 && acc[h] == 0) --h;
+  if (h < 0) return 0.0;
+  const int lead = 32 * h + 31 - __builtin_clz((unsigned)acc[h]);   // top bit, in units 2^-1074
+  double r;
+  if (lead < 53) {                                  // at most 53 bits: exact (subnormal or small normal)
+    const uint64_t n = (uint64_t)acc[0] | ((uint64_t)acc[1] << 32);
+    r = ldexp((double)n, -1074);
+  } else {
+    const int lo = lead - 63;                       // window of bits lo .. lead
+    uint64_t w = 0;
+    for (int q = 0; q < 3; ++q) {
+      const int k = (lo >> 5) + q;
+      const uint64_t d = (k >= 0 && k < kAccLimbs) ? (uint64_t)acc[k] : 0;
+      const int pos = 32 * q - (lo & 31);           // where digit k's bit 0 lands in the window
+      if (pos >= 0) { if (pos < 64) w |= d << pos; }
+      else w |= d >> (-pos);
+    }
+    uint64_t mant = w >> 11;                        // 53 bits, top one set
+    const bool half = (w >> 10) & 1;
+    bool sticky = (w & 0x3ff) != 0;
+    if (lo > 0) {                                   // bits below the window
+      const int kl = lo >> 5;
+      if ((uint64_t)acc[kl] & ((uint64_t(1) << (lo & 31)) - 1)) sticky = true;
+      for (int k = 0; k < kl && !sticky; ++k) sticky = acc[k] != 0;
+    }
+    if (half && (sticky || (mant & 1))) mant += 1;  // 2^53 stays exact
+    r = ldexp((double)mant, lo + 11 - 1074);
+  }
+  return neg ? -r : r;
 }
 
 // Orders this wavefront's LDS accesses around the point of the call.
@@ -168,7 +204,7 @@ __device__ __forceinline__ XSum xsum_merge(XSum x, XSum y) {
 }
 
 // Exactly rounded sum of v[0..TT) over the 64 lanes of a wavefront; every lane
-// gets the same value. scr: this wavefront's LDS scratch of at least 64 TT + 64
+// gets the same value. scr: this wavefront's LDS scratch of at least kAccLimbs
 // doubles, used only when the compensated sum is neither exact nor certified.
 template <int TT>
 __device__ __forceinline__ double wave_sum_exact(const double (&v)[TT], double *scr) {
@@ -183,17 +219,14 @@ __device__ __forceinline__ double wave_sum_exact(const double (&v)[TT], double *
   double r;
   if (x.exact && isfinite(x.s)) return x.s + x.c;
   if (certified_round(x.s, x.c, (int64_t)kWave * TT, r)) return r;
+  int64_t *acc = reinterpret_cast<int64_t *>(scr);
+  wave_sync_lds();
+  for (int k = lane; k < kAccLimbs; k += kWave) acc[k] = 0;
   wave_sync_lds();
 #pragma unroll
-  for (int t = 0; t < TT; ++t) scr[t * kWave + lane] = v[t];
+  for (int t = 0; t < TT; ++t) lacc_add(acc, v[t]);
   wave_sync_lds();
-  if (lane == 0) {
-    double *part = scr + kWave * TT;
-    int np = 0;
-    for (int k = 0; k < kWave * TT; ++k)
-      if (scr[k] != 0.0) partials_add(part, np, scr[k]);
-    r = partials_round(part, np);
-  }
+  if (lane == 0) r = lacc_round(acc);
   r = __shfl(r, 0);
   wave_sync_lds();
   return r;

@@ -86,28 +86,22 @@ __device__ __forceinline__ void block_stats(const T *__restrict__ X, int64_t ld,
   __syncthreads();
   if (!s_certified) {
     // The sum lies too close to a rounding boundary for the compensated pair to
-    // decide: thread 0 adds every square, split exactly into its rounded value
-    // and error, into exact partials, the workgroup staging the terms in LDS.
-    __shared__ double s_terms[2 * kThreads];
-    __shared__ double s_part[kMaxPartials];
-    int np = 0;
-    for (int e0 = 0; e0 < L * L; e0 += kThreads) {
-      const int e = e0 + tid;
+    // decide: every square, split exactly into its rounded value and error, goes
+    // into an exact long accumulator in LDS, then one thread rounds it once.
+    __shared__ int64_t s_acc[kAccLimbs];
+    for (int k = tid; k < kAccLimbs; k += kThreads) s_acc[k] = 0;
+    __syncthreads();
+    for (int e = tid; e < L * L; e += kThreads) {
       const int r = e / L, c = e - (e / L) * L;
-      double p = 0.0, pe = 0.0;
       if (r < vr && c < vc) {
         const double x = (double)X[(int64_t)r * ld + c];
-        p = x * x;
-        pe = __builtin_fma(x, x, -p);
+        const double p = x * x;
+        lacc_add(s_acc, p);
+        lacc_add(s_acc, __builtin_fma(x, x, -p));
       }
-      s_terms[2 * tid] = p;
-      s_terms[2 * tid + 1] = pe;
-      __syncthreads();
-      if (tid == 0)
-        for (int k = 0; k < 2 * kThreads; ++k) partials_add(s_part, np, s_terms[k]);
-      __syncthreads();
     }
-    if (tid == 0) s_sum = partials_round(s_part, np);
+    __syncthreads();
+    if (tid == 0) s_sum = lacc_round(s_acc);
   }
   if (tid == 0) {
     const StatAcc &t = s_w[0];
