@@ -150,14 +150,6 @@ tdg::GemmOperands operands_of(const tdgemm_plan_s *p) {
   g.tb = p->desc.trans_b != 0;
   g.pairs = reinterpret_cast<const tdgemm_pair *>(p->ws + p->ly.off_pairs);
   g.gsize = p->ly.gsize;
-  const tdgemm_desc &d = p->desc;
-  g.wmax = 1;
-  if (d.ctrl == TDGEMM_CTRL_SNR || d.ctrl == TDGEMM_CTRL_ACCEL) {
-    for (int w = 2; w <= 4; ++w)
-      if (d.w_allowed & (1u << w)) g.wmax = w;
-  } else {
-    g.wmax = d.fixed_w;
-  }
   return g;
 }
 
@@ -527,7 +519,6 @@ tdgemm_status tdgemm_calibrate(int32_t L, int32_t W, int32_t form, int32_t prec,
   g.pb.lda = g.pb.ldb = g.pb.ldc = L;
   g.pb.nI = n_inst; g.pb.nJ = 1; g.pb.nL = 1;
   g.gsize = 1;
-  g.wmax = W;
   g.pb.L = L;
   g.in_dtype = prec; g.prec = prec; g.form = form; g.ta = g.tb = false;
   g.pairs = pairs_w;

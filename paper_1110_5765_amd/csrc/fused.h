@@ -60,17 +60,20 @@ __device__ __forceinline__ void owner_of_packed_row(int ml, int W, int &g, int &
   else             { g = ml & 3;         r = ml >> 2; }
 }
 
-// L = 96: lane group g of a wavefront owns the 24 consecutive tile rows
-// 24 g .. 24 g + 23 (slot (a, g, r) holds row 24 g + 4 a + r), so the W
-// consecutive rows of an asymmetric word (W in {1, 2, 3, 4}) stay in one lane.
-// Packed row mb (W = 1: tile row) goes to the MFMA position that yields its
-// first slot: k = mb mod (24 / W) counts the words of lane group g. At W = 4
-// the six words of a lane group fill the first row block and half the second.
+// L = 96: a wavefront owns 48 tile rows (three row blocks); its lane group g
+// owns the 12 consecutive rows 12 g .. 12 g + 11 (slot (a, g, r) holds row
+// 12 g + 4 a + r), so the W consecutive rows of an asymmetric word (W in
+// {1, 2, 3, 4}, which all divide 12) stay in one lane. Packed row mb (W = 1:
+// tile row) belongs to wavefront row mb / (48 / W); within it, to lane group g
+// and word k = mb mod (12 / W), and goes to the MFMA position that yields that
+// word's first slot. The packed rows of wavefront row wr start at LDS row
+// 16 ceil(3 / W) wr (W = 1: 48 wr), where its MFMAs read them.
 template <typename PT, int W>
 __device__ __forceinline__ int lds_row_of96(int mb) {
-  constexpr int per = 24 / W;
-  const int g = mb / per, k = mb - g * per;
-  return 16 * (k >> 2) + mfma_pos<PT>(g, k & 3);
+  constexpr int per = 12 / W, rows = 48 / W, rbn = (3 + W - 1) / W;
+  const int wr = mb / rows, mw = mb - wr * rows;
+  const int g = mw / per, k = mw - g * per;
+  return 16 * rbn * wr + 16 * (k >> 2) + mfma_pos<PT>(g, k & 3);
 }
 
 template <typename PT>
@@ -80,42 +83,50 @@ __device__ __forceinline__ int lds_row_of(int m, int W) {
   return (m & ~15) + mfma_pos<PT>(g, r);
 }
 
-// K48 (L = 96 only): chunks of 48 raw columns, which are whole MFMA k-steps for
-// every W in {1, 2, 3, 4}; launched when a plan may hold W = 4. Without it L = 96
-// runs 24-column chunks and W in {1, 2, 3}.
-template <typename IT, typename PT, int L, int FORM, bool TA, bool TB, bool K48 = false>
+// threads of a workgroup: L / 16 wavefronts; at L = 96 twelve wavefronts of
+// 48 x 16, three on every SIMD
+template <int L>
+constexpr int fused_threads() { return L == 96 ? 768 : 4 * L; }
+
+template <typename IT, typename PT, int L, int FORM, bool TA, bool TB>
 struct Fused {
   static constexpr bool L96 = L == 96;
-  static_assert(!K48 || L96, "48-column chunks are the L = 96 variant with W = 4");
   // L = 128, FP64 packing: one workgroup per inner kernel (128 x 128), so each
   // subblock of A and B is companded and packed once per inner kernel. FP32
   // packing keeps two 128 x 64 slabs per inner kernel.
   static constexpr bool WIDE = L == 128 && sizeof(PT) == 8;
   static constexpr int TN = L96 ? 96 : (WIDE ? 128 : 64);  // output columns per workgroup
-  static constexpr int NT = 4 * L;        // threads: L / 16 wavefronts
+  static constexpr int NT = fused_threads<L>();
   static constexpr int WC = L96 ? 6 : 4;  // wavefront columns, 16 CB output columns each
-  static constexpr int RB = L96 ? 6 : 4;  // 16-row blocks per wavefront
+  static constexpr int RB = L96 ? 3 : 4;  // 16-row blocks per wavefront
   static constexpr int CB = WIDE ? 2 : 1; // 16-column blocks per wavefront
-  static constexpr int KC = (L == 64 || WIDE) ? 16 : (L96 ? (K48 ? 48 : 24) : 32);  // raw inner columns per chunk
-  static constexpr int VA = KC * L / NT;  // raw A values per thread per chunk
-  static constexpr int VB = KC * TN / NT; // raw B values per thread per chunk
-  static constexpr int WMAX = (L96 && !K48) ? 3 : 4;  // packings: {1, 2, WMAX}, and 3 at L = 96
+  // raw inner columns per chunk: at L = 96, 48 (whole MFMA k-steps for every W
+  // in {1, 2, 3, 4})
+  static constexpr int KC = (L == 64 || WIDE) ? 16 : (L96 ? 48 : 32);
+  // L = 96: the first half of the threads load A, the second half B, so that a
+  // thread holds 12 values of one operand, whole packed words for every W
+  static constexpr bool SPLIT = L96;
+  static constexpr int NLD = SPLIT ? NT / 2 : NT;  // threads loading each operand
+  static constexpr int VA = KC * L / NLD;  // raw A values per loading thread per chunk
+  static constexpr int VB = KC * TN / NLD; // raw B values per loading thread per chunk
+  static constexpr int WMAX = 4;           // packings {1, 2, 4}, and 3 at L = 96
   static constexpr bool HAS3 = L96;
   // packed accumulator sets: two let a pair's unpack overlap the next pair's
-  // MFMAs (L = 64); with one (L = 96 and 128, six row blocks or two column
-  // blocks per wavefront) a pair is unpacked right after its own MFMAs
+  // MFMAs (L = 64); with one (L = 96 and 128) a pair is unpacked right after
+  // its own MFMAs
   static constexpr int NACC = (L96 || WIDE) ? 1 : 2;
   // LDS row strides in elements. A 64-bit fragment read serves 32 lanes at a
   // time over 64 four-byte banks: lane groups g = 0, 1 read rows lc = 0..15 at
   // column g (A) or column lc of rows g (B). With SA = KC + 2 (2 mod 32) the 32
   // A reads start on distinct even banks; with SB = TN + 16 (16 mod 32) the two
   // B rows fall on opposite halves of the banks.
-  // K48: B rows are TN elements without padding (the two tiles would exceed the
-  // 160 KB of LDS); element (k, n) sits at column n ^ 16 (k & 1) instead, which
-  // puts the two B rows of a fragment read on opposite halves of the banks.
+  // L = 96: B rows are TN elements without padding (the two tiles would exceed
+  // the 160 KB of LDS); element (k, n) sits at column n ^ 16 (k & 1) instead,
+  // which puts the two B rows of a fragment read on opposite halves of the
+  // banks.
   static constexpr int SA = KC + 2;
-  static constexpr int SB = K48 ? TN : TN + 16;
-  static constexpr int bcol(int k, int n) { return K48 ? (n ^ ((k & 1) << 4)) : n; }
+  static constexpr int SB = L96 ? TN : TN + 16;
+  static constexpr int bcol(int k, int n) { return L96 ? (n ^ ((k & 1) << 4)) : n; }
   static constexpr int NCH = L / KC;      // chunks per pair
   // Symmetric form, A stored as given: four consecutive threads share a row and
   // thread i of the four holds columns 4i..4i+3 (and 4i+16..4i+19 when a chunk
@@ -125,18 +136,19 @@ struct Fused {
   static constexpr bool A_QUAD = FORM == TDGEMM_SYM && !TA;
   static constexpr bool A_SPLIT = A_QUAD && VA == 8;
   static constexpr int koffA(int v) { return A_SPLIT ? (v % 4) + 16 * (v / 4) : v; }
-  // register sets of raw loads: the prefetch distance in chunks (one at L = 96
-  // and 128, where the larger accumulator tiles leave fewer registers)
+  // register sets of raw loads: the prefetch distance in chunks (one at L = 128,
+  // where the 128 x 128 tile leaves fewer registers, and at L = 96, whose
+  // 48-column chunks hold a whole chunk of matrix work)
   static constexpr int PF = (L96 || WIDE) ? 1 : 2;
   typedef typename Mfma<PT>::Acc Acc;
-  static_assert(VA * NT == KC * L && VB * NT == KC * TN, "loads must cover a chunk");
+  static_assert(VA * NLD == KC * L && VB * NLD == KC * TN, "loads must cover a chunk");
   static_assert(KC % (4 * WMAX) == 0 && KC % 8 == 0 && (!HAS3 || KC % 12 == 0),
                 "packed chunk depth: whole k-steps");
   static_assert(VA % WMAX == 0 && VA % 2 == 0 && VB % WMAX == 0 && VB % 2 == 0 &&
                 (!HAS3 || (VA % 3 == 0 && VB % 3 == 0)),
                 "a thread's raw values form whole packed words");
-  static_assert(L96 ? (RB % 6 == 0) : (RB % WMAX == 0 && RB % 2 == 0),
-                "asymmetric words: whole row blocks (L = 96, W = 4: one and a half)");
+  static_assert(L96 ? (RB == 3) : (RB % WMAX == 0 && RB % 2 == 0),
+                "asymmetric words: whole row blocks (L = 96: 12 rows per lane group)");
   static_assert(NT == 64 * WC * (L / (16 * RB)), "wavefront grid covers the tile");
 
   struct Smem {
@@ -156,8 +168,14 @@ struct Fused {
   int b_n, b_k;           // (col, first row) of B's chunk
   int offA, offB;         // element offsets of (a_m, a_k) and (b_k, b_n) from the chunk corner
   bool a_row_ok, b_col_ok;
+  bool lda_thread;        // loads (and packs) A; with SPLIT the others load B
   Acc accR[NACC][RB][CB], accC[RB][CB];   // accR[P]: packed product of the pairs of parity P
-  PT ra[PF][VA], rb[PF][VB];
+  // raw values of the next chunks; with SPLIT a thread holds one operand's, in ra
+  PT ra[PF][VA], rb[SPLIT ? 1 : PF][SPLIT ? 1 : VB];
+  __device__ __forceinline__ PT &raw_b(int s, int q) {
+    if constexpr (SPLIT) return ra[s][q];
+    else return rb[s][q];
+  }
 
   __device__ __forceinline__ Fused(const Problem &pb_, const IT *A_, const IT *B_, Smem &sm_,
                                    int64_t r0_, int64_t c0_)
@@ -169,18 +187,21 @@ struct Fused {
     wr = (tid >> 6) / WC;
     wrow = wr * 16 * RB;
     wcol = ((tid >> 6) % WC) * 16 * CB;
+    lda_thread = !SPLIT || tid < NLD;
+    const int ta = tid;                               // index among the A loaders
+    const int tb = SPLIT ? tid - NLD : tid;           // index among the B loaders
     if (FORM == TDGEMM_SYM) {
       // 16 consecutive lanes take 16 consecutive rows, so that their LDS
       // stores hit distinct banks; the 4 lane groups of a wavefront cover the
       // 4 column segments of those rows
-      if (!TA) { a_m = tid >> 2;                         a_k = (tid & 3) * (A_SPLIT ? 4 : VA); }
-      else     { a_m = tid % L;                      a_k = (tid / L) * VA; }
+      if (!TA) { a_m = ta >> 2;                         a_k = (ta & 3) * (A_SPLIT ? 4 : VA); }
+      else     { a_m = ta % L;                      a_k = (ta / L) * VA; }
     } else {
-      if (!TA) { a_k = tid % KC;        a_m = (tid / KC) * VA; }
-      else     { a_k = tid / (L / VA);  a_m = (tid % (L / VA)) * VA; }
+      if (!TA) { a_k = ta % KC;        a_m = (ta / KC) * VA; }
+      else     { a_k = ta / (L / VA);  a_m = (ta % (L / VA)) * VA; }
     }
-    if (!TB) { b_n = tid % TN;         b_k = (tid / TN) * VB; }
-    else     { b_n = tid / (KC / VB);  b_k = (tid % (KC / VB)) * VB; }
+    if (!TB) { b_n = tb % TN;         b_k = (tb / TN) * VB; }
+    else     { b_n = tb / (KC / VB);  b_k = (tb % (KC / VB)) * VB; }
     offA = TA ? a_k * (int)pb.lda + a_m : a_m * (int)pb.lda + a_k;
     offB = TB ? b_n * (int)pb.ldb + b_k : b_k * (int)pb.ldb + b_n;
     a_row_ok = r0 + a_m < pb.M;
@@ -208,17 +229,21 @@ struct Fused {
     constexpr bool sym = FORM == TDGEMM_SYM;
     const int64_t stepA = sym ? (TA ? pb.lda : 1) : (TA ? 1 : pb.lda);
     const int64_t stepB = TB ? 1 : pb.ldb;
+    if (lda_thread) {
 #pragma unroll
-    for (int q = 0; q < VA; ++q) {
-      // symmetric: (row a_m, col a_k + q); asymmetric: (row a_m + q, col a_k)
-      bool ok = true;
-      if (CHECK) ok = sym ? (a_row_ok && a_k + koffA(q) < krem) : (a_m + q < mrem && a_k < krem);
-      ra[S][q] = ok ? (PT)(Ab + koffA(q) * stepA)[offA] : (PT)0;
+      for (int q = 0; q < VA; ++q) {
+        // symmetric: (row a_m, col a_k + q); asymmetric: (row a_m + q, col a_k)
+        bool ok = true;
+        if (CHECK) ok = sym ? (a_row_ok && a_k + koffA(q) < krem) : (a_m + q < mrem && a_k < krem);
+        ra[S][q] = ok ? (PT)(Ab + koffA(q) * stepA)[offA] : (PT)0;
+      }
     }
+    if (!SPLIT || !lda_thread) {
 #pragma unroll
-    for (int q = 0; q < VB; ++q) {
-      const bool ok = !CHECK || (b_col_ok && b_k + q < krem);
-      rb[S][q] = ok ? (PT)(Bb + q * stepB)[offB] : (PT)0;
+      for (int q = 0; q < VB; ++q) {
+        const bool ok = !CHECK || (b_col_ok && b_k + q < krem);
+        raw_b(S, q) = ok ? (PT)(Bb + q * stepB)[offB] : (PT)0;
+      }
     }
   }
 
@@ -254,14 +279,14 @@ struct Fused {
     } else {
       constexpr int u = U - units_a<W>();
       if (FORM == TDGEMM_SYM && W > 1) {
-        PT acc = compand<W>(rb[S][u * W + W - 1], cb);
+        PT acc = compand<W>(raw_b(S, u * W + W - 1), cb);
 #pragma unroll
-        for (int s = W - 2; s >= 0; --s) acc = __builtin_fma(acc, zi, compand<W>(rb[S][u * W + s], cb));
+        for (int s = W - 2; s >= 0; --s) acc = __builtin_fma(acc, zi, compand<W>(raw_b(S, u * W + s), cb));
         const int k = b_k / W + u;
         sm.b[buf][k * SB + bcol(k, b_n)] = acc;
       } else {
         const int k = b_k + u;
-        sm.b[buf][k * SB + bcol(k, b_n)] = compand<W>(rb[S][u], cb);
+        sm.b[buf][k * SB + bcol(k, b_n)] = compand<W>(raw_b(S, u), cb);
       }
     }
   }
@@ -276,7 +301,17 @@ struct Fused {
 
   template <int W, int S>
   __device__ __forceinline__ void store(int buf, PT ca, PT cb, PT z, PT zi) {
-    units<W, S, 0, units_a<W>() + units_b<W>()>(buf, ca, cb, z, zi);
+    if constexpr (SPLIT) {
+      // The LDS addresses of the words differ per W. Left loop-invariant, all of
+      // them would be hoisted out of the pair loop and kept live together (past
+      // the 168 registers of three wavefronts per SIMD); an empty asm statement
+      // makes the coordinates opaque here, so each W computes its own in place.
+      asm volatile("" : "+v"(a_m), "+v"(a_k), "+v"(b_n), "+v"(b_k));
+      if (lda_thread) units<W, S, 0, units_a<W>()>(buf, ca, cb, z, zi);
+      else units<W, S, units_a<W>(), units_a<W>() + units_b<W>()>(buf, ca, cb, z, zi);
+    } else {
+      units<W, S, 0, units_a<W>() + units_b<W>()>(buf, ca, cb, z, zi);
+    }
   }
 
   // The chunk's MFMAs into accumulator set P: packed depth KC / W (symmetric)
@@ -329,13 +364,13 @@ struct Fused {
             accC[a][b][r] = __builtin_fma(rr, inv, accC[a][b][r]);
           }
       } else if (L96) {                          // eqs. (13)-(14): W rows per word
-        // word k = 4 a + r of a lane group (k < 24 / W) yields its rows W k + s,
+        // word k = 4 a + r of a lane group (k < 12 / W) yields its rows W k + s,
         // in the slots (W k + s) / 4, register (W k + s) mod 4
 #pragma unroll
         for (int a = 0; a < (RB + W - 1) / W; ++a)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            if (4 * a + r >= 24 / W) continue;
+            if (4 * a + r >= 4 * RB / W) continue;
             PT t = accR[P][a][b][r];
 #pragma unroll
             for (int sl = 0; sl < W; ++sl) {
@@ -556,19 +591,19 @@ struct Fused {
       for (int b = 0; b < CB; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t row = r0 + wrow + (L96 ? 24 * lg + 4 * a : 16 * a + 4 * lg) + r;
+          const int64_t row = r0 + wrow + (L96 ? 12 * lg + 4 * a : 16 * a + 4 * lg) + r;
           const int64_t col = c0 + wcol + 16 * b + lc;
           if (row < pb.M && col < pb.N) C[row * ldc + col] = accC[a][b][r];
         }
   }
 };
 
-template <typename IT, typename PT, int L, int FORM, bool TA, bool TB, bool K48>
-__global__ __launch_bounds__(4 * L, (L == 64 ? 2 : 1)) void k_fused(GemmOperands g, const IT *__restrict__ A,
+template <typename IT, typename PT, int L, int FORM, bool TA, bool TB>
+__global__ __launch_bounds__(fused_threads<L>(), (L == 64 ? 2 : 1)) void k_fused(GemmOperands g, const IT *__restrict__ A,
                                                  const IT *__restrict__ B, PT *__restrict__ C,
                                                  PT *__restrict__ part, int64_t ntiles,
                                                  int64_t ngroups, int64_t per_xcd) {
-  typedef Fused<IT, PT, L, FORM, TA, TB, K48> F;
+  typedef Fused<IT, PT, L, FORM, TA, TB> F;
   __shared__ typename F::Smem sm;
   // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin, so give
   // each XCD a contiguous range. Groups of the l-sum are the slowest index, so
@@ -618,10 +653,10 @@ __global__ __launch_bounds__(256) void k_sum_groups(const PT *__restrict__ part,
 }
 
 // ---------------------------------------------------------------------------
-template <typename IT, typename PT, int L, int FORM, bool K48>
+template <typename IT, typename PT, int L, int FORM>
 static hipError_t launch_fused_t(const GemmOperands &g, const void *A, const void *B, void *C,
                                  void *part, hipStream_t st) {
-  typedef Fused<IT, PT, L, FORM, false, false, K48> F0;
+  typedef Fused<IT, PT, L, FORM, false, false> F0;
   const int64_t ntiles = g.pb.nI * g.pb.nJ * (L / F0::TN);
   const int64_t ngroups = (g.pb.nL + g.gsize - 1) / g.gsize;
   const int64_t per_xcd = (ntiles * ngroups + 7) / 8;
@@ -632,13 +667,13 @@ static hipError_t launch_fused_t(const GemmOperands &g, const void *A, const voi
   PT *c = (PT *)C;
   PT *p = (PT *)part;
   if (!g.ta && !g.tb)
-    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, false, false, K48>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
+    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, false, false>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
   else if (g.ta && !g.tb)
-    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, true, false, K48>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
+    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, true, false>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
   else if (!g.ta && g.tb)
-    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, false, true, K48>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
+    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, false, true>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
   else
-    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, true, true, K48>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
+    hipLaunchKernelGGL((k_fused<IT, PT, L, FORM, true, true>), grid, block, 0, st, g, a, b, c, p, ntiles, ngroups, per_xcd);
   if (ngroups > 1) {
     const int64_t n = g.pb.M * g.pb.N;
     hipLaunchKernelGGL((k_sum_groups<PT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, ngroups,
@@ -652,13 +687,8 @@ static hipError_t launch_fused_t(const GemmOperands &g, const void *A, const voi
 template <typename IT, typename PT, int L>
 hipError_t launch_fused_il(const GemmOperands &g, const void *A, const void *B, void *C, void *part,
                            hipStream_t st) {
-  if constexpr (L == 96) {
-    if (g.wmax == 4)                        // 48-column chunks: W in {1, 2, 3, 4}
-      return g.form == TDGEMM_SYM ? launch_fused_t<IT, PT, L, TDGEMM_SYM, true>(g, A, B, C, part, st)
-                                  : launch_fused_t<IT, PT, L, TDGEMM_ASYM, true>(g, A, B, C, part, st);
-  }
-  return g.form == TDGEMM_SYM ? launch_fused_t<IT, PT, L, TDGEMM_SYM, false>(g, A, B, C, part, st)
-                              : launch_fused_t<IT, PT, L, TDGEMM_ASYM, false>(g, A, B, C, part, st);
+  return g.form == TDGEMM_SYM ? launch_fused_t<IT, PT, L, TDGEMM_SYM>(g, A, B, C, part, st)
+                              : launch_fused_t<IT, PT, L, TDGEMM_ASYM>(g, A, B, C, part, st);
 }
 
 #define TDG_FUSED_INSTANCE(IT, PT, L)                                                         \

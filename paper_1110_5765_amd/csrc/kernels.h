@@ -52,7 +52,6 @@ struct GemmOperands {
   bool ta, tb;
   const tdgemm_pair *pairs;   // [n_pairs]
   int64_t gsize;              // subblocks per group of the l-sum (nL: one group)
-  int wmax;                   // largest packing the plan may hold
 };
 
 hipError_t launch_stats(const StatsArgs &a, int dtype, int L, hipStream_t st);

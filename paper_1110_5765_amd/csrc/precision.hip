@@ -118,6 +118,9 @@ __global__ __launch_bounds__(kThreads) void k_quant8(Quant8Args a) {
 // LDS rows are 128 bytes; the 16-byte chunk c of row r sits at chunk position
 // c ^ ((r >> 1) & 7). Sixteen lanes reading (or writing) 16 bytes each from
 // sixteen consecutive rows, or from two rows, then touch all 64 banks once.
+// Fourth word of a raw buffer resource on gfx9: 32-bit data format, no swizzle.
+constexpr int kBufWord3 = 0x00020000;
+
 __device__ __forceinline__ int swz8(int r, int c16) { return (c16 ^ ((r >> 1) & 7)) * 16; }
 
 template <int FMT, bool STAGED>
@@ -132,13 +135,25 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm8(Gemm8Args a) {
   const uint8_t *gA = a.qA + (i * kL8) * a.Kp;
   const uint8_t *gB = a.qB + (j * kL8) * a.Kp;
 
+  // Raw buffer loads: the operand panels as buffer resources, each thread's
+  // 16-byte chunks at fixed 32-bit offsets (r Kp + 16 c16 < 2^24, as Kp <= 2^16)
+  // and the subblock l as a scalar offset, so the loop computes no addresses.
   v4i stage[8];                            // 4 chunks of A, 4 of B (16 bytes each)
+  int goff[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int ch = tid + kThreads * q, r = ch >> 3, c16 = ch & 7;
+    goff[q] = (int)(r * a.Kp + c16 * 16);
+  }
+  const int span = (int)(kL8 * a.Kp);      // bytes of one 128-row panel
+  const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc((void *)gA, (short)0, span, kBufWord3);
+  const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc((void *)gB, (short)0, span, kBufWord3);
   auto gload = [&](int64_t l) {
+    const int so = (int)(l * kL8);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int ch = tid + kThreads * q, r = ch >> 3, c16 = ch & 7;
-      stage[q] = *reinterpret_cast<const v4i *>(gA + (int64_t)r * a.Kp + l * kL8 + c16 * 16);
-      stage[4 + q] = *reinterpret_cast<const v4i *>(gB + (int64_t)r * a.Kp + l * kL8 + c16 * 16);
+      stage[q] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rA, goff[q], so, 0));
+      stage[4 + q] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rB, goff[q], so, 0));
     }
   };
   auto sstore = [&](int buf) {
