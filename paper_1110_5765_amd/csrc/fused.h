@@ -169,6 +169,9 @@ struct Fused {
   int offA, offB;         // element offsets of (a_m, a_k) and (b_k, b_n) from the chunk corner
   bool a_row_ok, b_col_ok;
   bool lda_thread;        // loads (and packs) A; with SPLIT the others load B
+  // SPLIT: W-independent parts of this thread's LDS word addresses, from which
+  // each W forms its own with a few integer operations (see a_word, b_word)
+  int q0, q1, q2;
   Acc accR[NACC][RB][CB], accC[RB][CB];   // accR[P]: packed product of the pairs of parity P
   // raw values of the next chunks; with SPLIT a thread holds one operand's, in ra
   PT ra[PF][VA], rb[SPLIT ? 1 : PF][SPLIT ? 1 : VB];
@@ -206,6 +209,17 @@ struct Fused {
     offB = TB ? b_n * (int)pb.ldb + b_k : b_k * (int)pb.ldb + b_n;
     a_row_ok = r0 + a_m < pb.M;
     b_col_ok = c0 + b_n < pb.N;
+    if constexpr (SPLIT) {
+      // a_k is a multiple of 12 and so are a_m (asymmetric) and b_k: the 12 / W
+      // words of a thread are consecutive words of one row run (symmetric A),
+      // of one lane group (asymmetric A) or of one column (B)
+      if (lda_thread) {
+        if (FORM == TDGEMM_SYM) { q0 = a_row<1>(a_m) * SA; q1 = a_k / 12; q2 = 0; }
+        else { q0 = a_m / 48; q1 = mfma_pos<PT>((a_m % 48) / 12, 0); q2 = a_k; }
+      } else {
+        q0 = b_k / 12; q1 = b_n; q2 = 0;
+      }
+    }
 #pragma unroll
     for (int a = 0; a < RB; ++a)
 #pragma unroll
@@ -267,6 +281,29 @@ struct Fused {
     else return lds_row_of<PT>(mb, W);
   }
 
+  // LDS element index of word u of this thread (A: unit u, B: unit u past A's)
+  template <int W, int u>
+  __device__ __forceinline__ int a_word(void) const {
+    if constexpr (SPLIT) {
+      if constexpr (FORM == TDGEMM_SYM) return q0 + q1 * (12 / W) + u;
+      constexpr int rbn = (RB + W - 1) / W;      // the same row as lds_row_of96<PT, W>
+      return (16 * rbn * q0 + q1 + 16 * (u >> 2) + mfma_pos<PT>(0, u & 3)) * SA + q2;
+    } else {
+      if constexpr (FORM == TDGEMM_SYM) return a_row<1>(a_m) * SA + (a_k + koffA(u * W)) / W;
+      else return a_row<W>(a_m / W + u) * SA + a_k;
+    }
+  }
+  template <int W, int u>
+  __device__ __forceinline__ int b_word(void) const {
+    if constexpr (SPLIT) {
+      const int k = ((FORM == TDGEMM_SYM && W > 1) ? q0 * (12 / W) : q0 * 12) + u;
+      return k * SB + bcol(k, q1);
+    } else {
+      const int k = ((FORM == TDGEMM_SYM && W > 1) ? b_k / W : b_k) + u;
+      return k * SB + bcol(k, b_n);
+    }
+  }
+
   template <int W, int S, int U>
   __device__ __forceinline__ void unit(int buf, PT ca, PT cb, PT z, PT zi) {
     if (U < units_a<W>()) {
@@ -274,19 +311,16 @@ struct Fused {
       PT acc = compand<W>(ra[S][u * W + W - 1], ca);
 #pragma unroll
       for (int s = W - 2; s >= 0; --s) acc = __builtin_fma(acc, z, compand<W>(ra[S][u * W + s], ca));
-      if (FORM == TDGEMM_SYM) sm.a[buf][a_row<1>(a_m) * SA + (a_k + koffA(u * W)) / W] = acc;
-      else                    sm.a[buf][a_row<W>(a_m / W + u) * SA + a_k] = acc;
+      sm.a[buf][a_word<W, u>()] = acc;
     } else {
       constexpr int u = U - units_a<W>();
       if (FORM == TDGEMM_SYM && W > 1) {
         PT acc = compand<W>(raw_b(S, u * W + W - 1), cb);
 #pragma unroll
         for (int s = W - 2; s >= 0; --s) acc = __builtin_fma(acc, zi, compand<W>(raw_b(S, u * W + s), cb));
-        const int k = b_k / W + u;
-        sm.b[buf][k * SB + bcol(k, b_n)] = acc;
+        sm.b[buf][b_word<W, u>()] = acc;
       } else {
-        const int k = b_k + u;
-        sm.b[buf][k * SB + bcol(k, b_n)] = compand<W>(raw_b(S, u), cb);
+        sm.b[buf][b_word<W, u>()] = compand<W>(raw_b(S, u), cb);
       }
     }
   }
@@ -302,11 +336,11 @@ struct Fused {
   template <int W, int S>
   __device__ __forceinline__ void store(int buf, PT ca, PT cb, PT z, PT zi) {
     if constexpr (SPLIT) {
-      // The LDS addresses of the words differ per W. Left loop-invariant, all of
-      // them would be hoisted out of the pair loop and kept live together (past
-      // the 168 registers of three wavefronts per SIMD); an empty asm statement
-      // makes the coordinates opaque here, so each W computes its own in place.
-      asm volatile("" : "+v"(a_m), "+v"(a_k), "+v"(b_n), "+v"(b_k));
+      // Left loop-invariant, the word addresses of all four W would be hoisted
+      // out of the pair loop and kept live together, past the 168 registers of
+      // three wavefronts per SIMD; an empty asm statement makes their inputs
+      // opaque here, so each W forms its own (a few integer operations) in place.
+      asm volatile("" : "+v"(q0), "+v"(q1), "+v"(q2));
       if (lda_thread) units<W, S, 0, units_a<W>()>(buf, ca, cb, z, zi);
       else units<W, S, units_a<W>(), units_a<W>() + units_b<W>()>(buf, ca, cb, z, zi);
     } else {
