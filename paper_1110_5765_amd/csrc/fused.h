@@ -1,19 +1,17 @@
 // Fused throughput-distortion GEMM: every stage of a subblock pair in one
 // kernel (Sec. 3 with the settings of Sec. 5.B / Sec. 6).
 //
-// A workgroup computes an L x TN slab of one inner kernel R_ij (the whole
-// inner kernel, TN = L, but for FP32 packing at L = 128: TN = 64) and walks its pairs
-// l in ascending order -- all of them, or one group of consecutive l when the
-// l-sum is split (the group sums are then added in order by k_sum_groups).
-// Each pair's K
-// extent is cut into chunks of KC raw columns (16, 24 or 48). For every chunk
-// the threads load raw A / B values from HBM one or two chunks ahead, compand
-// them (eq. 3) and pack them (eqs. 6-7, or 11) into a double-buffered LDS
-// tile; each wavefront then runs FP64 (or FP32) 16x16x4 MFMAs for its
-// 16 RB x 16 CB part of the tile, accumulating the packed product over the
-// packed index in ascending order. After a pair's last chunk the packed
-// result is unpacked in registers (eqs. 9-10 or 13-14), reverse-companded
-// (eq. 5) and added to a register-resident C tile (eq. 2) as
+// A workgroup computes one inner kernel R_ij (an L x L tile of C) and walks
+// its pairs l in ascending order -- all of them, or one group of consecutive l
+// when the l-sum is split (the group sums are then added in order by
+// k_sum_groups). Each pair's K extent is cut into chunks of KC raw columns (16
+// or 48). For every chunk the threads load raw A / B values from HBM one or two
+// chunks ahead, compand them (eq. 3) and pack them (eqs. 6-7, or 11) into a
+// double-buffered LDS tile; each wavefront then runs FP64 (or FP32) 16x16x4
+// MFMAs for its 16 RB x 16 CB part of the tile, accumulating the packed product
+// over the packed index in ascending order. After a pair's last chunk the
+// packed result is unpacked in registers (eqs. 9-10 or 13-14),
+// reverse-companded (eq. 5) and added to a register-resident C tile (eq. 2) as
 // C = fma(r, inv, C), one rounding per pair. W = 1 pairs run the plain
 // product. C (or the group's partial result) is written once at the end.
 //
@@ -91,10 +89,9 @@ constexpr int fused_threads() { return L == 96 ? 768 : 4 * L; }
 template <typename IT, typename PT, int L, int FORM, bool TA, bool TB>
 struct Fused {
   static constexpr bool L96 = L == 96;
-  // L = 128, FP64 packing: one workgroup per inner kernel (128 x 128), so each
-  // subblock of A and B is companded and packed once per inner kernel. FP32
-  // packing keeps two 128 x 64 slabs per inner kernel.
-  static constexpr bool WIDE = L == 128 && sizeof(PT) == 8;
+  // L = 128: one workgroup per inner kernel (128 x 128), so each subblock of A
+  // and B is companded and packed once per inner kernel
+  static constexpr bool WIDE = L == 128;
   static constexpr int TN = L96 ? 96 : (WIDE ? 128 : 64);  // output columns per workgroup
   static constexpr int NT = fused_threads<L>();
   static constexpr int WC = L96 ? 6 : 4;  // wavefront columns, 16 CB output columns each

@@ -199,11 +199,11 @@ def make_desc(A: torch.Tensor, B: torch.Tensor, *, L: int = 64, form: str = "sym
 def auto_k_split(M: int, N: int, K: int, L: int, prec: str = "f64", workgroups: int = 512) -> int:
     """A k_split that gives about `workgroups` fused workgroups when M and N leave
     fewer than 256 of them (one per CU); 1 otherwise. The fused kernel runs one
-    workgroup per inner kernel, two with FP32 packing at L = 128 (`prec`, the
-    packing precision). Only the order of the l-sum changes, in the way
+    workgroup per inner kernel at every L and packing precision (`prec` is kept
+    for callers that name it). Only the order of the l-sum changes, in the way
     tdgemm_desc.k_split describes."""
     nI, nJ, nL = -(-M // L), -(-N // L), -(-K // L)
-    tiles = max(1, nI * nJ * (2 if (L == 128 and prec == "f32") else 1))
+    tiles = max(1, nI * nJ)
     if nL <= 1 or tiles >= 256:
         return 1
     return max(1, min(nL, -(-workgroups // tiles)))
