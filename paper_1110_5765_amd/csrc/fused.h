@@ -348,9 +348,8 @@ struct Fused {
   // The chunk's MFMAs into accumulator set P: packed depth KC / W (symmetric)
   // or KC (asymmetric, W = 1). Wavefront (wr, wc) multiplies packed row blocks
   // of its 64 output rows by its column blocks. B fragment rows are 4 ks + lg,
-  // of the parity of lg. FIRST: the pair's first chunk, whose first k-step
-  // starts from zero instead of the accumulator.
-  template <int W, int P, bool FIRST = false>
+  // of the parity of lg.
+  template <int W, int P>
   __device__ __forceinline__ void mma(int buf) {
     constexpr bool SYMW = (FORM == TDGEMM_SYM) || W == 1;
     constexpr int NKS = SYMW ? KC / (4 * W) : KC / 4;
@@ -370,7 +369,7 @@ struct Fused {
       for (int a = 0; a < RBN; ++a)
 #pragma unroll
         for (int b = 0; b < CB; ++b)
-          accR[P][a][b] = Mfma<PT>::mma(af[a], bf[b], (FIRST && ks == 0) ? Mfma<PT>::zero() : accR[P][a][b]);
+          accR[P][a][b] = Mfma<PT>::mma(af[a], bf[b], accR[P][a][b]);
       __builtin_amdgcn_sched_barrier(0);
     });
   }
@@ -444,14 +443,10 @@ struct Fused {
           }
       }
     }
-    // two accumulator sets: cleared here; one: the next pair's first MFMAs
-    // start from zero (every accumulator the unpack reads is written first)
-    if constexpr (NACC == 2) {
 #pragma unroll
-      for (int a = 0; a < RB; ++a)
+    for (int a = 0; a < RB; ++a)
 #pragma unroll
-        for (int b = 0; b < CB; ++b) accR[P][a][b] = Mfma<PT>::zero();
-    }
+      for (int b = 0; b < CB; ++b) accR[P][a][b] = Mfma<PT>::zero();
   }
 
   struct PairState {
@@ -543,8 +538,8 @@ struct Fused {
   template <bool CHECK, int W>
   __device__ __forceinline__ void pair_w(int64_t l, int64_t total, const PairState &ps) {
     const int64_t g0 = l * NCH;
-    // chunks kc and kc + 1; the pair's first chunk (kc = 0, h = 0) is peeled
-    auto two = [&](int kc, auto firstc) {
+#pragma unroll 1
+    for (int kc = 0; kc < NCH; kc += 2) {
       static_for<0, 2>([&](auto hc) {
         constexpr int h = decltype(hc)::value;   // LDS buffer of chunk g0 + kc + h
         constexpr int S = PF == 2 ? h : 0;        // register set of its raw values
@@ -553,12 +548,9 @@ struct Fused {
         const int64_t g = g0 + kc + h;
         const int64_t g2 = g + PF < total ? g + PF : total - 1;
         load<CHECK, S>((g2 / NCH) * L + (g2 % NCH) * KC);
-        mma<W, 0, decltype(firstc)::value && h == 0>(h);
+        mma<W, 0>(h);
       });
-    };
-    two(0, std::true_type());
-#pragma unroll 1
-    for (int kc = 2; kc < NCH; kc += 2) two(kc, std::false_type());
+    }
     finish<W, 0>(ps.inv, ps.z, ps.zi);
   }
 
