@@ -378,21 +378,29 @@ __device__ __forceinline__ tdgemm_pair option_separable(int W, double L_eff, con
 // approximate minimum (relative error below 1e-6); the exact formula is then
 // evaluated, in ascending order, at every point within a relative 1e-5 of it,
 // so the result equals a full exact scan.
+//
+// The scan may be shared by LP lanes (a power of two; the aligned group of LP
+// lanes holding the same pair): lane `sub` of the group scans the points
+// sub, sub + LP, ...; the FP32 minimum and then the exact (value, index) pair,
+// lowest index on equal values, are reduced over the group. Minima are exact,
+// so every group lane gets the serial scan's result.
 __device__ __forceinline__ int argmin_nsr(double L_eff, const BlockMoments &a, const BlockMoments &b,
                                           const double *r, const double *s, const short *idx,
-                                          const float *fr, const float *fs2, int cnt) {
+                                          const float *fr, const float *fs2, int cnt,
+                                          int sub = 0, int LP = 1) {
   const double ss = a.sigma * b.sigma;
   const float x0 = (float)(((L_eff * a.amax) * b.amax) / ss);   // c_tot * R / (s_a s_b)
   const float invL = 1.0f / (float)L_eff;
   float best = INFINITY;
-  for (int i = 0; i < cnt; ++i) {
+  for (int i = sub; i < cnt; i += LP) {
     const float x = x0 * fr[i];
     best = fminf(best, x * ((1.0f / 6.0f) + x * ((1.0f / 144.0f) + fs2[i] * invL)));
   }
+  for (int off = 1; off < LP; off <<= 1) best = fminf(best, __shfl_xor(best, off));
   const float thr = (best < INFINITY) ? best * (1.0f + 1e-5f) : INFINITY;
   int kbest = -1;
   double vbest = INFINITY;
-  for (int i = 0; i < cnt; ++i) {
+  for (int i = sub; i < cnt; i += LP) {
     const float x = x0 * fr[i];
     const float v = x * ((1.0f / 6.0f) + x * ((1.0f / 144.0f) + fs2[i] * invL));
     if (v <= thr) {
@@ -400,6 +408,11 @@ __device__ __forceinline__ int argmin_nsr(double L_eff, const BlockMoments &a, c
       const double e = nsr_exact(L_eff, a.amax, b.amax, ss, r[k], s[k]);
       if (e < vbest) { vbest = e; kbest = k; }
     }
+  }
+  for (int off = 1; off < LP; off <<= 1) {
+    const double ov = __shfl_xor(vbest, off);
+    const int ok = __shfl_xor(kbest, off);
+    if (ov < vbest || (ov == vbest && ok >= 0 && (kbest < 0 || ok < kbest))) { vbest = ov; kbest = ok; }
   }
   return kbest;
 }

@@ -275,6 +275,13 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
   double sigv[TT];                                // signal terms of the Sec. 6 budget
   // this wavefront's LDS: the entries of the bisection, or the terms of an exact sum
   double *scr = sh_ent[threadIdx.x / kWave];
+  // With one subblock per lane (nL <= 64), LP lanes share each subblock's
+  // table scans (the plan is latency-bound and the scans are its longest
+  // chains): subblock l is computed by lanes l LP .. l LP + LP - 1 and its
+  // results are moved to lane l afterwards.
+  int LP = 1;
+  if (TT == 1)
+    while (LP < 16 && 2 * LP * pb.nL <= kWave) LP *= 2;
 #pragma unroll
   for (int t = 0; t < TT; ++t) {
     level[t] = 0;
@@ -288,19 +295,44 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
     const BlockMoments ma = moments(a.stats_a[i * pb.nL + l]);
     const BlockMoments mb = moments(a.stats_b[l * pb.nJ + j]);
     sigv[t] = (L_eff * (ma.sigma * ma.sigma)) * (mb.sigma * mb.sigma);
-    if (!snr || ma.amax == 0.0 || mb.amax == 0.0) continue;   // D = 0
-#pragma unroll 1
-    for (int v = 0; v < a.n_opt; ++v) {
-      const int W = a.w_desc[v];
-      if (W == 1) continue;                       // D = 0
-      const int q = srow(W);
-      const double *s = a.calib_s + q * a.n_r;
-      const int k = argmin_nsr(L_eff, ma, mb, a.calib_r, s, sh_idx[q], sh_fr[q], sh_fs2[q], sh_cnt[q]);
-      const double d = (k < 0) ? kDUnavailable
-                               : option_at(W, L_eff, ma, mb, a.calib_r[k], s[k], a.u_safe).d;
+  }
 #pragma unroll
-      for (int u = 0; u < kMaxOpt; ++u)
-        if (u == v) { dopt[u][t] = d; kopt[u][t] = k; }
+  for (int t = 0; t < TT; ++t) {
+    if (t >= T) continue;
+    const int64_t l = (TT == 1) ? lane / LP : lane + (int64_t)kWave * t;   // subblock of this lane
+    const int sub = (TT == 1) ? (lane & (LP - 1)) : 0;
+    double dg[kMaxOpt];
+    int kg[kMaxOpt];
+#pragma unroll
+    for (int v = 0; v < kMaxOpt; ++v) { dg[v] = 0.0; kg[v] = -1; }
+    if (l < pb.nL && snr) {
+      const double L_eff = (double)min<int64_t>(pb.L, pb.K - l * pb.L);
+      const BlockMoments ma = moments(a.stats_a[i * pb.nL + l]);
+      const BlockMoments mb = moments(a.stats_b[l * pb.nJ + j]);
+      if (ma.amax != 0.0 && mb.amax != 0.0) {     // else D = 0
+#pragma unroll 1
+        for (int v = 0; v < a.n_opt; ++v) {
+          const int W = a.w_desc[v];
+          if (W == 1) continue;                   // D = 0
+          const int q = srow(W);
+          const double *s = a.calib_s + q * a.n_r;
+          const int k = argmin_nsr(L_eff, ma, mb, a.calib_r, s, sh_idx[q], sh_fr[q], sh_fs2[q], sh_cnt[q],
+                                   sub, LP);
+          const double d = (k < 0) ? kDUnavailable
+                                   : option_at(W, L_eff, ma, mb, a.calib_r[k], s[k], a.u_safe).d;
+#pragma unroll
+          for (int u = 0; u < kMaxOpt; ++u)
+            if (u == v) { dg[u] = d; kg[u] = k; }
+        }
+      }
+    }
+    const bool own = lane + (int64_t)kWave * t < pb.nL;
+#pragma unroll
+    for (int v = 0; v < kMaxOpt; ++v) {
+      const double dv = (TT == 1) ? __shfl(dg[v], lane * LP) : dg[v];
+      const int kv = (TT == 1) ? __shfl(kg[v], lane * LP) : kg[v];
+      dopt[v][t] = own ? dv : 0.0;
+      kopt[v][t] = own ? kv : -1;
     }
   }
 
