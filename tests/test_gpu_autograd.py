@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from oracle import pipeline as pl
-from tests.gpu_common import device_calib, log, oracle_cfg, rel_err
+from tests.gpu_common import assert_elementwise, device_calib, log, oracle_cfg, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -65,10 +65,16 @@ def test_packed_gradients_vs_oracle_and_fp64(ag, snr):
         ks = td.auto_k_split(a.shape[0], b.shape[1], a.shape[1], L, "f32")
         return pl.run(a, b, dataclasses.replace(ocfg, k_groups=ks), calib=tabs).C
 
-    ref = {"Y": oracle(X, W), "dX": oracle(G, W.T.copy()), "dW": oracle(X.T.copy(), G)}
+    operands = {"Y": (X, W), "dX": (G, W.T.copy()), "dW": (X.T.copy(), G)}
+    ref = {k: oracle(a, b) for k, (a, b) in operands.items()}
     exact = {"Y": X.astype(np.float64) @ W, "dX": G.astype(np.float64) @ W.T.astype(np.float64),
              "dW": X.T.astype(np.float64) @ G}
     for k in ("Y", "dX", "dW"):
+        # bit for bit with the oracle's grouping of the l-sum, and element by element
+        # within 1e-5 |A||B| of eq. (2) as one ascending sum
+        np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
+        a, b = operands[k]
+        assert_elementwise(got[k], pl.run(a, b, ocfg, calib=tabs).C, a, b, 1e-5, f"{k} vs the ascending l-sum")
         assert rel_err(got[k], ref[k]) <= 1e-5, k
         s = pl.snr_db(got[k].astype(np.float64), exact[k])
         log(f"[autograd] S={snr:g}: {k} SNR vs FP64 {s:.2f} dB")

@@ -13,7 +13,7 @@ import pytest
 
 import workloads
 from oracle import pipeline as pl
-from tests.gpu_common import device_calib, log, oracle_cfg, rel_err, to_dev
+from tests.gpu_common import assert_elementwise, device_calib, log, oracle_cfg, rel_err, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -56,6 +56,11 @@ def test_pca2d_gemms(td, snr):
     G_ref = pl.run(np.ascontiguousarray(S.T), S, dataclasses.replace(cfg, k_groups=ks(Sd.t(), Sd)),
                    calib=tabs).C
     G = lib(Sd.t(), Sd)
+    # bit for bit with the oracle's grouping of the l-sum, element by element within
+    # 1e-5 |A||B| of eq. (2) as one ascending sum
+    St = np.ascontiguousarray(S.T)
+    np.testing.assert_array_equal(G, G_ref)
+    assert_elementwise(G, pl.run(St, S, cfg, calib=tabs).C, St, S, 1e-5, "G vs the ascending l-sum")
     assert rel_err(G, G_ref) <= 1e-5
     _, V = np.linalg.eigh(G_ref.astype(np.float64))
     X = np.ascontiguousarray(V[:, ::-1][:, :d]).astype(np.float32)
@@ -63,6 +68,10 @@ def test_pca2d_gemms(td, snr):
     Ys_ref = pl.run(S, X, dataclasses.replace(cfg, k_groups=ks(Sd, Xd)), calib=tabs).C
     Yt_ref = pl.run(T, X, dataclasses.replace(cfg, k_groups=ks(Td, Xd)), calib=tabs).C
     Ys, Yt = lib(Sd, Xd), lib(Td, Xd)
+    np.testing.assert_array_equal(Ys, Ys_ref)
+    np.testing.assert_array_equal(Yt, Yt_ref)
+    assert_elementwise(Ys, pl.run(S, X, cfg, calib=tabs).C, S, X, 1e-5, "Ys vs the ascending l-sum")
+    assert_elementwise(Yt, pl.run(T, X, cfg, calib=tabs).C, T, X, 1e-5, "Yt vs the ascending l-sum")
     assert rel_err(Ys, Ys_ref) <= 1e-5 and rel_err(Yt, Yt_ref) <= 1e-5
 
     def match(ys, yt):
