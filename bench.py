@@ -654,6 +654,9 @@ def run_mlp(args):
     cfg = autograd.TDConfig(L=L, form=args.form, prec="f32", ctrl="snr", snr_db=args.mlp_snr,
                             w_allowed=(1, 2), min_dim=2 * L)
     tdc = autograd.TDContext(cfg, calib)
+    # the same layer with its products in the INT8 block-scaled form (Remark 1)
+    tdc8 = autograd.TDContext(autograd.TDConfig(L=128, prec="i8", ctrl="separable", sep_q=127.0,
+                                                min_dim=128), None)
     X = torch.from_numpy(xs).cuda()
     Y = torch.from_numpy(ys).cuda()
     nsteps = args.mlp_steps
@@ -670,7 +673,10 @@ def run_mlp(args):
     def forward(params, x, packed):
         h = x
         for k, (W, b) in enumerate(params):
-            h = autograd.TDLinearFn.apply(h, W, b, tdc) if packed else h @ W + b
+            if packed:
+                h = autograd.TDLinearFn.apply(h, W, b, tdc8 if packed == "i8" else tdc)
+            else:
+                h = h @ W + b
             if k + 1 < len(params):
                 h = torch.relu(h)
         return h
@@ -706,6 +712,7 @@ def run_mlp(args):
     ms_p, loss_p = train(True)
     packed_calls = (tdc.calls - calls0) / (nsteps + 3)
     ms_q, loss_q = train(False)
+    ms_8, loss_8 = train("i8")
     # distortion of one packed product of the trained shape (forward of layer 2)
     h = torch.randn(xs.shape[1], 1024, device="cuda")
     W2 = torch.from_numpy(Ws[1]).cuda()
@@ -721,9 +728,15 @@ def run_mlp(args):
     for k, (fi, fo) in enumerate(sizes):
         flops += 2.0 * B * fi * fo * (3 if k > 0 else 2)        # forward, dW (+ dX past layer 1)
     gap = max(abs(a - b) for a, b in zip(loss_p, loss_q))
+    gap8 = max(abs(a - b) for a, b in zip(loss_8, loss_q))
+    C8 = tdc8.matmul(h, W2)
+    err8 = C8.double() - ref
+    snr8 = 10.0 * math.log10(float((ref * ref).sum()) / float((err8 * err8).sum()))
     log(f"[bench] packed {ms_p:.3f} ms/step ({packed_calls:.0f} packed products per step), plain "
         f"{ms_q:.3f} ms/step; loss packed {loss_p[0]:.4f} -> {loss_p[-1]:.4f}, plain {loss_q[0]:.4f} -> "
         f"{loss_q[-1]:.4f}, max gap {gap:.4f}; layer-2 product SNR {snr:.1f} dB, W {wh}")
+    log(f"[bench] INT8 block-scaled products: {ms_8:.3f} ms/step ({ms_q / ms_8:.2f}x the plain step); loss "
+        f"{loss_8[0]:.4f} -> {loss_8[-1]:.4f}, max gap to plain {gap8:.4f}; layer-2 product SNR {snr8:.1f} dB")
     out = {
         "metric": "effective GFLOP/s at fixed output SNR vs plain FP64 GEMM; % of FP64 MFMA peak",
         "value": round(flops / ms_p / 1e6, 1),
@@ -747,6 +760,11 @@ def run_mlp(args):
         "max_loss_gap": round(gap, 5),
         "product_snr_db": round(snr, 2),
         "product_w_histogram": wh,
+        "int8_block_scaled_ms_per_step": round(ms_8, 4),
+        "int8_block_scaled_gflops": round(flops / ms_8 / 1e6, 1),
+        "loss_int8_block_scaled": [round(v, 5) for v in loss_8[:: max(1, nsteps // 20)]] + [round(loss_8[-1], 5)],
+        "max_loss_gap_int8": round(gap8, 5),
+        "int8_product_snr_db": round(snr8, 2),
         "roofline": None,
         "cpu_baseline": None,
     }

@@ -81,6 +81,33 @@ def test_packed_gradients_vs_oracle_and_fp64(ag, snr):
         assert s >= snr - 3.0, (k, s)
 
 
+def test_int8_block_scaled_layer_vs_oracle(ag):
+    """prec "i8": the layer's three products in the INT8 block-scaled form
+    (Remark 1) equal the oracle's block-scaled product bit for bit (ragged
+    shapes, transposed operands as views); their SNR against FP64 is logged."""
+    from oracle import precision as pr
+    autograd, td = ag
+    cfg = autograd.TDConfig(L=128, prec="i8", ctrl="separable", sep_q=127.0, min_dim=64)
+    tdc = autograd.TDContext(cfg, None)
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((300, 200)).astype(np.float32)
+    W = (rng.standard_normal((200, 260)) / math.sqrt(200)).astype(np.float32)
+    G = rng.laplace(0.0, 1.0, (300, 260)).astype(np.float32)
+    Xd = torch.from_numpy(X).cuda().requires_grad_()
+    Wd = torch.from_numpy(W).cuda().requires_grad_()
+    Y = autograd.TDLinearFn.apply(Xd, Wd, None, tdc)
+    Y.backward(torch.from_numpy(G).cuda())
+    torch.cuda.synchronize()
+    assert tdc.calls == 3 and tdc.plain_calls == 0
+    got = {"Y": Y.detach().cpu().numpy(), "dX": Xd.grad.cpu().numpy(), "dW": Wd.grad.cpu().numpy()}
+    operands = {"Y": (X, W), "dX": (G, W.T.copy()), "dW": (X.T.copy(), G)}
+    for k, (a, b) in operands.items():
+        ref = pr.run(a.astype(np.float64), b.astype(np.float64), 128, "i8", 127.0).C
+        np.testing.assert_array_equal(got[k], ref, err_msg=k)
+        exact = a.astype(np.float64) @ b.astype(np.float64)
+        log(f"[autograd] INT8 block-scaled {k}: SNR vs FP64 {pl.snr_db(got[k].astype(np.float64), exact):.2f} dB")
+
+
 def test_mlp_steps_track_plain(ag):
     """A 512 -> 256 -> 10 perceptron, 20 SGD steps from the same start: the
     packed model's loss follows the plain FP32 model's closely and decreases."""
