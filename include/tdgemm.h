@@ -54,7 +54,8 @@ enum { TDGEMM_CTRL_SNR = 0, TDGEMM_CTRL_FIXED = 1, TDGEMM_CTRL_SEPARABLE = 2, TD
 
 typedef struct {
   int64_t M, N, K;
-  int64_t lda, ldb, ldc;       /* L * lda and L * ldb must be below 2^31
+  int64_t lda, ldb, ldc;       /* L * lda and L * ldb times the element size of
+                                 in_dtype must be below 2^30 bytes
                                  (TDGEMM_E_UNSUPPORTED otherwise) */
   int32_t trans_a, trans_b;   /* 0 or 1, see conventions */
   int32_t in_dtype;           /* TDGEMM_F64 or TDGEMM_F32: element type of A and B */

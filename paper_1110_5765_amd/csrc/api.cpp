@@ -16,7 +16,7 @@ using tdg::layout_of;
 
 bool is_finite(double x) { return std::isfinite(x); }
 
-constexpr int64_t kMaxTileSpan = int64_t(1) << 31;   // L * lda and L * ldb must stay below
+constexpr int64_t kMaxTileBytes = int64_t(1) << 30;  // L * lda and L * ldb, in bytes, must stay below
 
 bool valid_l(int L) { return L == 64 || L == 96 || L == 128; }
 
@@ -59,8 +59,10 @@ tdgemm_status validate_desc(const tdgemm_desc *d) {
   if (d->lda < (need_a > 0 ? need_a : 1) || d->ldb < (need_b > 0 ? need_b : 1) ||
       d->ldc < (d->N > 0 ? d->N : 1))
     return TDGEMM_E_ARG;
-  // the fused kernel addresses an element of a tile by a 32-bit offset below L * ld
-  if ((int64_t)d->L * d->lda >= kMaxTileSpan || (int64_t)d->L * d->ldb >= kMaxTileSpan)
+  // the fused kernel reads L rows (or columns) of an operand as one buffer
+  // resource, by 32-bit byte offsets below L * ld * element size
+  const int64_t esz = d->in_dtype == TDGEMM_F64 ? 8 : 4;
+  if ((int64_t)d->L * d->lda * esz >= kMaxTileBytes || (int64_t)d->L * d->ldb * esz >= kMaxTileBytes)
     return TDGEMM_E_UNSUPPORTED;
   if (!(d->u_safe > 0.0) || !is_finite(d->u_safe)) return TDGEMM_E_ARG;
   switch (d->ctrl) {

@@ -16,6 +16,8 @@ constexpr int kThreads = 256;          // threads per workgroup of every kernel
 constexpr int kWave = 64;              // CDNA wavefront width
 constexpr double kDUnavailable = 1e300;  // D of an option the calibration cannot supply
 constexpr int kMaxR = 512;             // calibration grid points
+// Fourth word of a raw buffer resource on gfx9: 32-bit data format, no swizzle.
+constexpr int kBufWord3 = 0x00020000;
 
 // Workgroup barrier that orders LDS accesses only: global loads a thread has in
 // flight stay in flight (a plain __syncthreads also waits for them, which

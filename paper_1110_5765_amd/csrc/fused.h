@@ -163,7 +163,7 @@ struct Fused {
   // per-thread load coordinates inside a chunk
   int a_m, a_k;           // first (row, col) this thread loads from A's chunk
   int b_n, b_k;           // (col, first row) of B's chunk
-  int offA, offB;         // element offsets of (a_m, a_k) and (b_k, b_n) from the chunk corner
+  int offA, offB;         // byte offsets of (a_m, a_k) and (b_k, b_n) from the chunk corner
   bool a_row_ok, b_col_ok;
   bool lda_thread;        // loads (and packs) A; with SPLIT the others load B
   // SPLIT: W-independent parts of this thread's LDS word addresses, from which
@@ -202,8 +202,8 @@ struct Fused {
     }
     if (!TB) { b_n = tb % TN;         b_k = (tb / TN) * VB; }
     else     { b_n = tb / (KC / VB);  b_k = (tb % (KC / VB)) * VB; }
-    offA = TA ? a_k * (int)pb.lda + a_m : a_m * (int)pb.lda + a_k;
-    offB = TB ? b_n * (int)pb.ldb + b_k : b_k * (int)pb.ldb + b_n;
+    offA = (TA ? a_k * (int)pb.lda + a_m : a_m * (int)pb.lda + a_k) * (int)sizeof(IT);
+    offB = (TB ? b_n * (int)pb.ldb + b_k : b_k * (int)pb.ldb + b_n) * (int)sizeof(IT);
     a_row_ok = r0 + a_m < pb.M;
     b_col_ok = c0 + b_n < pb.N;
     if constexpr (SPLIT) {
@@ -225,13 +225,29 @@ struct Fused {
       }
   }
 
-  // Raw loads of the chunk starting at inner index k0: a uniform base pointer
-  // plus this thread's fixed offset. With CHECK, out-of-range elements read 0.
+  // One raw value: a buffer load from the chunk corner's resource, at this
+  // thread's byte offset plus the value's uniform (scalar) byte offset, so no
+  // load needs a per-lane 64-bit address.
+  __device__ __forceinline__ static PT raw_load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    if constexpr (sizeof(IT) == 8)
+      return (PT)__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    else
+      return (PT)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  }
+
+  // Raw loads of the chunk starting at inner index k0: the chunk corner as a
+  // buffer resource spanning L rows (or columns) of the operand, plus this
+  // thread's fixed offset (L ld sizeof(IT) < 2^30, checked on the host). With
+  // CHECK, out-of-range elements read 0 and are never loaded.
   template <bool CHECK, int S>
   __device__ __forceinline__ void load(int64_t kc0) {
     const int64_t k0 = kb + kc0;
     const IT *Ab = TA ? A + k0 * pb.lda + r0 : A + r0 * pb.lda + k0;
     const IT *Bb = TB ? B + c0 * pb.ldb + k0 : B + k0 * pb.ldb + c0;
+    const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)Ab, (short)0, (int)((int64_t)L * pb.lda * (int64_t)sizeof(IT)), kBufWord3);
+    const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)Bb, (short)0, (int)((int64_t)L * pb.ldb * (int64_t)sizeof(IT)), kBufWord3);
     const int64_t kleft = pb.K - k0, mleft = pb.M - r0;
     const int krem = CHECK ? (int)(kleft < KC ? kleft : KC) : KC;     // valid inner columns (may be <= 0)
     const int mrem = CHECK ? (int)(mleft < L ? mleft : L) : L;        // valid rows of the tile
@@ -240,20 +256,35 @@ struct Fused {
     constexpr bool sym = FORM == TDGEMM_SYM;
     const int64_t stepA = sym ? (TA ? pb.lda : 1) : (TA ? 1 : pb.lda);
     const int64_t stepB = TB ? 1 : pb.ldb;
+    // symmetric A as stored: a thread's values are consecutive in memory, G to
+    // a 16-byte load (runs of 4 for koffA)
+    constexpr int G = 16 / (int)sizeof(IT);
+    constexpr bool WIDE_A = sym && !TA && VA % G == 0 && (!A_SPLIT || G <= 4);
     if (lda_thread) {
+      if constexpr (WIDE_A && !CHECK) {
+        typedef IT vec_t __attribute__((ext_vector_type(G)));
 #pragma unroll
-      for (int q = 0; q < VA; ++q) {
-        // symmetric: (row a_m, col a_k + q); asymmetric: (row a_m + q, col a_k)
-        bool ok = true;
-        if (CHECK) ok = sym ? (a_row_ok && a_k + koffA(q) < krem) : (a_m + q < mrem && a_k < krem);
-        ra[S][q] = ok ? (PT)(Ab + koffA(q) * stepA)[offA] : (PT)0;
+        for (int q = 0; q < VA; q += G) {
+          const vec_t v = __builtin_bit_cast(
+              vec_t, __builtin_amdgcn_raw_buffer_load_b128(rA, offA, koffA(q) * (int)sizeof(IT), 0));
+#pragma unroll
+          for (int e = 0; e < G; ++e) ra[S][q + e] = (PT)v[e];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < VA; ++q) {
+          // symmetric: (row a_m, col a_k + q); asymmetric: (row a_m + q, col a_k)
+          bool ok = true;
+          if (CHECK) ok = sym ? (a_row_ok && a_k + koffA(q) < krem) : (a_m + q < mrem && a_k < krem);
+          ra[S][q] = ok ? raw_load(rA, offA, (int)(koffA(q) * stepA * (int64_t)sizeof(IT))) : (PT)0;
+        }
       }
     }
     if (!SPLIT || !lda_thread) {
 #pragma unroll
       for (int q = 0; q < VB; ++q) {
         const bool ok = !CHECK || (b_col_ok && b_k + q < krem);
-        raw_b(S, q) = ok ? (PT)(Bb + q * stepB)[offB] : (PT)0;
+        raw_b(S, q) = ok ? raw_load(rB, offB, (int)(q * stepB * (int64_t)sizeof(IT))) : (PT)0;
       }
     }
   }

@@ -118,9 +118,6 @@ __global__ __launch_bounds__(kThreads) void k_quant8(Quant8Args a) {
 // LDS rows are 128 bytes; the 16-byte chunk c of row r sits at chunk position
 // c ^ ((r >> 1) & 7). Sixteen lanes reading (or writing) 16 bytes each from
 // sixteen consecutive rows, or from two rows, then touch all 64 banks once.
-// Fourth word of a raw buffer resource on gfx9: 32-bit data format, no swizzle.
-constexpr int kBufWord3 = 0x00020000;
-
 __device__ __forceinline__ int swz8(int r, int c16) { return (c16 ^ ((r >> 1) & 7)) * 16; }
 
 template <int FMT, bool STAGED>

@@ -105,9 +105,12 @@ def _desc(binding, **kw):
     ({"ctrl": 4}, 0), ({"ctrl": 4, "snr_db": -math.inf}, -1), ({"ctrl": 4, "fixed_rmax": -1.0}, -1),
     ({"ctrl": 4, "fixed_w": 3}, -1), ({"ctrl": 4, "snr_db": math.inf}, 0),
     ({"k_split": -1}, -1), ({"k_split": 3}, 0), ({"k_split": 1000}, 0),
-    # L * lda or L * ldb at 2^31 and above: beyond the fused kernel's 32-bit tile offsets
-    ({"lda": (1 << 31) // 64}, -2), ({"lda": (1 << 31) // 64 - 1}, 0),
-    ({"ldb": (1 << 31) // 128, "L": 128}, -2), ({"ldb": (1 << 31) // 128 - 1, "L": 128}, 0),
+    # L * lda or L * ldb at 2^30 bytes and above: beyond the fused kernel's 32-bit
+    # buffer offsets (FP64 elements of 8 bytes, FP32 of 4)
+    ({"lda": (1 << 30) // (64 * 8)}, -2), ({"lda": (1 << 30) // (64 * 8) - 1}, 0),
+    ({"ldb": (1 << 30) // (128 * 8), "L": 128}, -2), ({"ldb": (1 << 30) // (128 * 8) - 1, "L": 128}, 0),
+    ({"ldb": (1 << 30) // (128 * 4), "L": 128, "in_dtype": 1, "prec": 1}, -2),
+    ({"ldb": (1 << 30) // (128 * 4) - 1, "L": 128, "in_dtype": 1, "prec": 1}, 0),
     # measured saved-time units of the throughput control (Sec. 5.B F_W)
     ({"ctrl": 3, "accel": 0.5, "accel_units": (0, 0, 1365, 0, 2000)}, 0),
     ({"ctrl": 3, "accel_units": (0, 7, 1365, 0, 2000)}, -1), ({"ctrl": 3, "accel_units": (0, 0, -1, 0, 0)}, -1),
