@@ -142,15 +142,34 @@ def main():
     return run_sweep(args)
 
 
+class _Joined:
+    """A step's start event that is the previous step's end event: recording it
+    again is a no-op, so back-to-back steps record one event between them."""
+
+    def __init__(self, ev):
+        self.ev = ev
+
+    def record(self, stream=None):
+        pass
+
+    def elapsed_time(self, other):
+        return self.ev.elapsed_time(other)
+
+
 def timed_steps(torch, step, warmup, steps, phases):
     """W untimed steps, then exactly K timed steps between device synchronisations.
-    step(ev) records events ev[0..phases] on the current stream between its phases.
+    step(ev) records events ev[0..phases] on the current stream between its phases;
+    ev[0] of a step is the previous step's ev[phases] (each event recorded on the
+    stream costs a few microseconds of idle GPU between the kernels it separates).
     Returns (ms per step by the host clock, [per-phase mean ms])."""
     import numpy as np
     for _ in range(warmup):
         step(None)
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(phases + 1)] for _ in range(steps)]
+    evs = []
+    for k in range(steps):
+        first = torch.cuda.Event(enable_timing=True) if k == 0 else _Joined(evs[k - 1][phases])
+        evs.append([first] + [torch.cuda.Event(enable_timing=True) for _ in range(phases)])
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     for k in range(steps):

@@ -124,9 +124,12 @@ __device__ __forceinline__ void lacc_add(int64_t *acc, double x) {
 
 // One thread: the accumulated sum rounded once to nearest, ties to even. The
 // limbs are normalised in place (digits in [0, 2^32), the magnitude if the sum
-// is negative).
-__device__ inline double lacc_round(int64_t *acc) {
+// is negative). Out of line and with rolled loops: it is the rare path of every
+// exact sum, and inlined copies of the unrolled limb loops made the plan kernel
+// three times longer.
+__device__ __noinline__ double lacc_round(int64_t *acc) {
   int64_t carry = 0;
+#pragma unroll 1
   for (int k = 0; k < kAccLimbs; ++k) {
     const int64_t v = acc[k] + carry;
     carry = v >> 32;                                // floor division by 2^32
@@ -135,6 +138,7 @@ __device__ inline double lacc_round(int64_t *acc) {
   const bool neg = carry < 0;                       // the sum is carry 2^(32 kAccLimbs) + digits
   if (neg) {                                        // magnitude: two's complement of the digits
     int64_t c = 1;
+#pragma unroll 1
     for (int k = 0; k < kAccLimbs; ++k) {
       const int64_t v = (0xffffffffll - acc[k]) + c;
       c = v >> 32;
@@ -394,6 +398,7 @@ __device__ __forceinline__ int argmin_nsr(double L_eff, const BlockMoments &a, c
   const float x0 = (float)(((L_eff * a.amax) * b.amax) / ss);   // c_tot * R / (s_a s_b)
   const float invL = 1.0f / (float)L_eff;
   float best = INFINITY;
+#pragma unroll 4
   for (int i = sub; i < cnt; i += LP) {
     const float x = x0 * fr[i];
     best = fminf(best, x * ((1.0f / 6.0f) + x * ((1.0f / 144.0f) + fs2[i] * invL)));
@@ -402,6 +407,7 @@ __device__ __forceinline__ int argmin_nsr(double L_eff, const BlockMoments &a, c
   const float thr = (best < INFINITY) ? best * (1.0f + 1e-5f) : INFINITY;
   int kbest = -1;
   double vbest = INFINITY;
+#pragma unroll 4
   for (int i = sub; i < cnt; i += LP) {
     const float x = x0 * fr[i];
     const float v = x * ((1.0f / 6.0f) + x * ((1.0f / 144.0f) + fs2[i] * invL));

@@ -429,6 +429,7 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
 #pragma unroll
         for (int t = 0; t < TT; ++t) rank[v][t] = (v < n_ent && dopt[v][t] > 0.0) ? 0 : INT_MAX;
       const int nslot = n_ent * T * kWave;
+#pragma unroll 4
       for (int sidx = 0; sidx < nslot; ++sidx) {
         const double ds = ent[sidx];
         const int ls = ((sidx / kWave) % T) * kWave + (sidx & (kWave - 1));
