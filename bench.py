@@ -359,7 +359,8 @@ def run_sweep_table(args):
                         if ev is not None:
                             ev[1].record(stream)
 
-                    ms, _ = timed_steps(torch, step, 2, max(5, args.steps // 2), 1)
+                    # five warm-up steps: the clocks drop while the host evaluates a point
+                    ms, _ = timed_steps(torch, step, 5, max(10, args.steps // 2), 1)
                     _, _, pairs, _ = td.tdgemm_plan_export(holder["plan"])
                     wh = {int(w): int((pairs["w"] == w).sum()) for w in wset}
                     snr = snr_of(torch, C, ref)

@@ -668,26 +668,54 @@ __global__ __launch_bounds__(fused_threads<L>(), (L == 64 ? 2 : 1)) void k_fused
   typedef Fused<IT, PT, L, FORM, TA, TB> F;
   __shared__ typename F::Smem sm;
   // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin, so give
-  // each XCD a contiguous range. Groups of the l-sum are the slowest index, so
-  // the workgroups running together on one XCD sum the same subblocks l; tiles
-  // go a few tile-rows at a time, so that they share A panels and B slabs in
-  // that XCD's L2.
+  // each XCD a contiguous range. Tiles go a few tile-rows at a time, so that the
+  // workgroups running together on one XCD share A panels and B slabs in its L2.
   // A workgroup covers L rows and a TN-column slab of one inner kernel.
   const int64_t bid = blockIdx.x;
-  const int64_t lin = (bid & 7) * per_xcd + (bid >> 3);
-  if (lin >= ntiles * ngroups) return;
-  const int64_t grp_l = lin / ntiles;              // group of the l-sum
-  const int64_t tlin = lin - grp_l * ntiles;
   const Problem &pb = g.pb;
   constexpr int64_t SLABS = L / F::TN;
   const int64_t nS = pb.nJ * SLABS;
   constexpr int64_t GROUP = (L == 64) ? 8 : 4;    // tile rows per group: an XCD's
-  const int64_t grp = tlin / (GROUP * nS);         // concurrent workgroups form a GROUP x 8 block
-  const int64_t first_i = grp * GROUP;
-  const int64_t gsize = min(GROUP, pb.nI - first_i);
-  const int64_t in_grp = tlin - grp * GROUP * nS;
-  const int64_t ti = first_i + in_grp % gsize;
-  const int64_t ts = in_grp / gsize;
+  // tile t of a rows x cols grid in that order: concurrent workgroups form a GROUP x 8 block
+  auto by_groups = [](int64_t t, int64_t rows, int64_t cols, int64_t &ti, int64_t &ts) {
+    const int64_t grp = t / (GROUP * cols);
+    const int64_t first_i = grp * GROUP;
+    const int64_t gsize = min(GROUP, rows - first_i);
+    const int64_t in_grp = t - grp * GROUP * cols;
+    ti = first_i + in_grp % gsize;
+    ts = in_grp / gsize;
+  };
+  int64_t grp_l = 0, ti, ts;
+  if (ngroups > 1) {
+    // groups of the l-sum are the slowest index, so the workgroups running
+    // together on one XCD sum the same subblocks l
+    const int64_t lin = (bid & 7) * per_xcd + (bid >> 3);
+    if (lin >= ntiles * ngroups) return;
+    grp_l = lin / ntiles;
+    by_groups(lin - grp_l * ntiles, pb.nI, nS, ti, ts);
+  } else {
+    // XCD x runs tiles [T0, T1) of the order, per_xcd of them; of those, a
+    // share of the border tiles (ragged M or N, less work) proportional to the
+    // count comes last, so that when the tiles do not fill a whole number of
+    // rounds the last round is made of the short ones.
+    const int64_t nIf = pb.M / L, nSf = pb.N / F::TN;
+    const int64_t nF = nIf * nSf, nB = ntiles - nF;
+    const int64_t x = bid & 7, k = bid >> 3;
+    const int64_t T0 = min(x * per_xcd, ntiles), T1 = min((x + 1) * per_xcd, ntiles);
+    const int64_t b0 = nB * T0 / ntiles, nb = nB * T1 / ntiles - b0;
+    const int64_t f0 = T0 - b0, nf = (T1 - T0) - nb;
+    if (k < nf) {
+      by_groups(f0 + k, nIf, nSf, ti, ts);
+    } else if (k < nf + nb) {
+      // border tiles: the last slab column over the full tile rows, then the last tile row
+      const int64_t t = b0 + (k - nf);
+      const int64_t ncol = nS > nSf ? nIf : 0;
+      if (t < ncol) { ti = t; ts = nS - 1; }
+      else { ti = pb.nI - 1; ts = t - ncol; }
+    } else {
+      return;
+    }
+  }
   const int64_t tj = ts / SLABS;
   const int64_t l0 = grp_l * g.gsize;
   const int64_t nl = min(g.gsize, pb.nL - l0);
