@@ -422,26 +422,46 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
         for (int t = 0; t < TT; ++t)
           if (v < n_ent && t < T) ent[(v * T + t) * kWave + lane] = dopt[v][t];
       wave_sync_lds();
-      // rank of each own entry with D > 0: entries with a larger D, or equal D and lower l
+      // rank of each own entry with D > 0: entries with a larger D, or equal D and
+      // lower l (only entries with D > 0 can be counted). The count runs over the
+      // n_ent levels in use, compiled for each count, with no test of validity
+      // inside the loop; entries that are not ranked get INT_MAX afterwards.
       int rank[kMaxOpt - 1][TT];
-#pragma unroll
-      for (int v = 0; v < kMaxOpt - 1; ++v)
-#pragma unroll
-        for (int t = 0; t < TT; ++t) rank[v][t] = (v < n_ent && dopt[v][t] > 0.0) ? 0 : INT_MAX;
       const int nslot = n_ent * T * kWave;
+      auto count_above = [&](auto nec) {
+        constexpr int NE = decltype(nec)::value;
+        int cnt[NE][TT];
+#pragma unroll
+        for (int v = 0; v < NE; ++v)
+#pragma unroll
+          for (int t = 0; t < TT; ++t) cnt[v][t] = 0;
 #pragma unroll 4
-      for (int sidx = 0; sidx < nslot; ++sidx) {
-        const double ds = ent[sidx];
-        const int ls = ((sidx / kWave) % T) * kWave + (sidx & (kWave - 1));
+        for (int sidx = 0; sidx < nslot; ++sidx) {
+          const double ds = ent[sidx];
+          const int ls = ((sidx / kWave) % T) * kWave + (sidx & (kWave - 1));
+#pragma unroll
+          for (int t = 0; t < TT; ++t) {
+            const bool lower = ls < t * kWave + lane;
+#pragma unroll
+            for (int v = 0; v < NE; ++v) {
+              const double de = dopt[v][t];
+              cnt[v][t] += (ds > de || (ds == de && lower)) ? 1 : 0;
+            }
+          }
+        }
 #pragma unroll
         for (int v = 0; v < kMaxOpt - 1; ++v)
 #pragma unroll
           for (int t = 0; t < TT; ++t) {
-            const double de = dopt[v][t];
-            const int le = t * kWave + lane;
-            if (ds > de || (ds == de && ls < le)) rank[v][t] += (rank[v][t] != INT_MAX) ? 1 : 0;
+            int c = 0;
+#pragma unroll
+            for (int u = 0; u < NE; ++u) if (u == v) c = cnt[u][t];
+            rank[v][t] = (v < n_ent && dopt[v][t] > 0.0) ? c : INT_MAX;
           }
-      }
+      };
+      if (n_ent == 1)      count_above(std::integral_constant<int, 1>{});
+      else if (n_ent == 2) count_above(std::integral_constant<int, 2>{});
+      else                 count_above(std::integral_constant<int, 3>{});
       // n_unav: entries with D >= kDUnavailable, ranked first; the greedy removes
       // them whatever the budget
       int n_pos = 0, n_unav = 0;
