@@ -256,13 +256,15 @@ struct Fused {
     constexpr bool sym = FORM == TDGEMM_SYM;
     const int64_t stepA = sym ? (TA ? pb.lda : 1) : (TA ? 1 : pb.lda);
     const int64_t stepB = TB ? 1 : pb.ldb;
-    // symmetric A as stored: a thread's values are consecutive in memory, G to
-    // a 16-byte load (runs of 4 for koffA)
+    // Where a thread's values are consecutive in memory (symmetric A as stored,
+    // asymmetric A transposed, B transposed), G of them come in one 16-byte load
+    // (runs of 4 for koffA).
     constexpr int G = 16 / (int)sizeof(IT);
-    constexpr bool WIDE_A = sym && !TA && VA % G == 0 && (!A_SPLIT || G <= 4);
+    constexpr bool WIDE_A = (sym != TA) && VA % G == 0 && (!A_SPLIT || G <= 4);
+    constexpr bool WIDE_B = TB && VB % G == 0;
+    typedef IT vec_t __attribute__((ext_vector_type(G)));
     if (lda_thread) {
       if constexpr (WIDE_A && !CHECK) {
-        typedef IT vec_t __attribute__((ext_vector_type(G)));
 #pragma unroll
         for (int q = 0; q < VA; q += G) {
           const vec_t v = __builtin_bit_cast(
@@ -281,10 +283,20 @@ struct Fused {
       }
     }
     if (!SPLIT || !lda_thread) {
+      if constexpr (WIDE_B && !CHECK) {
 #pragma unroll
-      for (int q = 0; q < VB; ++q) {
-        const bool ok = !CHECK || (b_col_ok && b_k + q < krem);
-        raw_b(S, q) = ok ? raw_load(rB, offB, (int)(q * stepB * (int64_t)sizeof(IT))) : (PT)0;
+        for (int q = 0; q < VB; q += G) {
+          const vec_t v = __builtin_bit_cast(
+              vec_t, __builtin_amdgcn_raw_buffer_load_b128(rB, offB, q * (int)sizeof(IT), 0));
+#pragma unroll
+          for (int e = 0; e < G; ++e) raw_b(S, q + e) = (PT)v[e];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < VB; ++q) {
+          const bool ok = !CHECK || (b_col_ok && b_k + q < krem);
+          raw_b(S, q) = ok ? raw_load(rB, offB, (int)(q * stepB * (int64_t)sizeof(IT))) : (PT)0;
+        }
       }
     }
   }
