@@ -698,7 +698,16 @@ __global__ __launch_bounds__(fused_threads<L>(), (L == 64 ? 2 : 1)) void k_fused
     ts = in_grp / gsize;
   };
   int64_t grp_l = 0, ti, ts;
-  if (ngroups > 1) {
+  // Each XCD runs per_xcd tiles, one per CU at a time (two at L = 64). When its last round
+  // is full or at least half full, the border tiles (ragged M or N, less work)
+  // of its share go last, in proportion to the share's size, so that the short
+  // tiles end the launch. With only a few tiles in the last round, the row
+  // order is kept: there the border tiles are better run beside the full tiles
+  // of their own rows, whose operand panels the XCD's L2 still holds (measured
+  // on 4000^3 and 3900^3 at L = 128 and on 4000^3, 4050^3, 4096^3 at L = 96).
+  constexpr int64_t per_round = (L == 64) ? 64 : 32;   // workgroups an XCD runs at once
+  const int64_t last = per_xcd % per_round;
+  if (ngroups > 1 || (last != 0 && last < per_round / 2)) {
     // groups of the l-sum are the slowest index, so the workgroups running
     // together on one XCD sum the same subblocks l
     const int64_t lin = (bid & 7) * per_xcd + (bid >> 3);
@@ -706,10 +715,8 @@ __global__ __launch_bounds__(fused_threads<L>(), (L == 64 ? 2 : 1)) void k_fused
     grp_l = lin / ntiles;
     by_groups(lin - grp_l * ntiles, pb.nI, nS, ti, ts);
   } else {
-    // XCD x runs tiles [T0, T1) of the order, per_xcd of them; of those, a
-    // share of the border tiles (ragged M or N, less work) proportional to the
-    // count comes last, so that when the tiles do not fill a whole number of
-    // rounds the last round is made of the short ones.
+    // XCD x runs tiles [T0, T1) of the order; of those, a share of the border
+    // tiles proportional to the count comes last
     const int64_t nIf = pb.M / L, nSf = pb.N / F::TN;
     const int64_t nF = nIf * nSf, nB = ntiles - nF;
     const int64_t x = bid & 7, k = bid >> 3;
