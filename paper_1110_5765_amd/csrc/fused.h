@@ -191,9 +191,9 @@ struct Fused {
     const int ta = tid;                               // index among the A loaders
     const int tb = SPLIT ? tid - NLD : tid;           // index among the B loaders
     if (FORM == TDGEMM_SYM) {
-      // 16 consecutive lanes take 16 consecutive rows, so that their LDS
-      // stores hit distinct banks; the 4 lane groups of a wavefront cover the
-      // 4 column segments of those rows
+      // A as stored: four consecutive lanes share a row (16-byte loads of
+      // consecutive columns, see A_QUAD); A transposed: consecutive lanes take
+      // consecutive rows, which are consecutive in memory
       if (!TA) { a_m = ta >> 2;                         a_k = (ta & 3) * (A_SPLIT ? 4 : VA); }
       else     { a_m = ta % L;                      a_k = (ta / L) * VA; }
     } else {
