@@ -247,6 +247,50 @@ SPLIT_CASES = [
 ]
 
 
+# Shapes whose tiles fill the last round of an XCD (one tile per CU at L = 96 and
+# 128, two at L = 64) at least half: the fused launch runs each XCD's border
+# tiles last. Ragged M and N, so there are border tiles on both edges.
+ORDER_CASES = [
+    # name, M, K, N, L, form; tiles per XCD (ceil(tiles / 8)) and its last round
+    ("order_L64_256tiles", 1014, 128, 1014, 64, "sym"),      # 256 tiles: 32 per XCD, 32 of 64
+    ("order_L128_121tiles", 1388, 256, 1388, 128, "sym"),    # 121 tiles: 16 per XCD, 16 of 32
+    ("order_L96_121tiles", 1026, 192, 1026, 96, "asym"),     # 121 tiles: 16 per XCD, 16 of 32
+    ("order_L128_row_order", 1100, 256, 1300, 128, "sym"),   # 99 tiles: 13 per XCD, row order
+]
+
+
+@pytest.mark.parametrize("case", ORDER_CASES, ids=[c[0] for c in ORDER_CASES])
+def test_fused_tile_order_parity(td, case):
+    """The fused kernel's tile order (border tiles last in each XCD's share, or
+    the row order) covers every tile once: C equals the staged path and the
+    oracle bit for bit."""
+    name, M, K, N, L, form = case
+    log(f"[order] {name}: M={M} K={K} N={N} L={L} {form}")
+    A, B, Ad, Bd = _inputs(M, K, N, np.float64, 0, 0, seed=zlib.crc32(name.encode()))
+    wal = (1, 2, 3) if L == 96 else (1, 2, 4)
+    calib, tabs = device_calib(td, L, form, "f64", tuple(w for w in wal if w > 1))
+    cfg = oracle_cfg(L, form, "f64", "snr", 30.0, wal, 2, 0.0, 127.0)
+    res = pl.run(A, B, cfg, calib=tabs)
+    desc = td.make_desc(Ad, Bd, L=L, form=form, prec="f64", ctrl="snr", snr_db=30.0, w_allowed=wal)
+    plan = td.tdgemm_plan(desc, Ad, Bd, calib)
+    C_fu = torch.full((M, N), float("nan"), dtype=torch.float64, device="cuda")
+    td.tdgemm_gemm(plan, Ad, Bd, C_fu, fused=1)
+    n = td.slot_elems(plan)
+    bufs = {k: torch.full((n,), float("nan"), dtype=torch.float64, device="cuda") for k in
+            ("qA", "qB", "pA", "pB", "R", "r")}
+    C_st = torch.full((M, N), float("nan"), dtype=torch.float64, device="cuda")
+    td.tdgemm_compand(plan, Ad, Bd, bufs["qA"], bufs["qB"])
+    td.tdgemm_pack(plan, bufs["qA"], bufs["qB"], bufs["pA"], bufs["pB"])
+    td.tdgemm_gemm(plan, bufs["pA"], bufs["pB"], bufs["R"], fused=0)
+    td.tdgemm_unpack(plan, bufs["R"], bufs["r"], C_st)
+    torch.cuda.synchronize()
+    Cf, Cs = C_fu.cpu().numpy(), C_st.cpu().numpy()
+    assert np.all(np.isfinite(Cf))
+    np.testing.assert_array_equal(Cf, Cs)
+    np.testing.assert_array_equal(Cf, res.C, err_msg="C vs oracle")
+    nI, nL, nJ, _ = plan.dims
+    log(f"[order] {name}: {nI * nJ} tiles, C bit-exact against the staged path and the oracle")
+
 @pytest.mark.parametrize("case", SPLIT_CASES, ids=[c[0] for c in SPLIT_CASES])
 def test_k_split_parity(td, case):
     """The l-sum of eq. (2) in groups of consecutive subblocks (k_split): the fused
