@@ -209,19 +209,54 @@ __device__ __forceinline__ XSum xsum_merge(XSum x, XSum y) {
   return XSum{s, c, x.exact & y.exact & ((e1 == 0.0 && e2 == 0.0) ? 1 : 0)};
 }
 
+// Partner values for step OFF of a wavefront all-reduce whose steps run in the
+// order 1, 2, 4, 8, 16, 32. Steps 1 and 2 swap neighbours within a quad and
+// steps 4 and 8 mirror each half-row and row, all as DPP moves; by then every
+// lane of a group already holds its group's result, so any lane of the partner
+// group will do. Steps 16 and 32 use ds_bpermute. Every lane must be active.
+template <int OFF>
+__device__ __forceinline__ int lane_partner(int v) {
+  if constexpr (OFF == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);    // quad_perm 1,0,3,2
+  else if constexpr (OFF == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+  else if constexpr (OFF == 4) return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false); // row_half_mirror
+  else if constexpr (OFF == 8) return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false); // row_mirror
+  else return __shfl_xor(v, OFF);
+}
+template <int OFF>
+__device__ __forceinline__ double lane_partner(double v) {
+  const int64_t b = __double_as_longlong(v);
+  const int lo = lane_partner<OFF>((int)(uint32_t)b), hi = lane_partner<OFF>((int)(b >> 32));
+  return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+template <int OFF>
+__device__ __forceinline__ XSum xsum_step(XSum x) {
+  return xsum_merge(x, XSum{lane_partner<OFF>(x.s), lane_partner<OFF>(x.c), lane_partner<OFF>(x.exact)});
+}
+__device__ __forceinline__ double lane0(double v) {
+  const int64_t b = __double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 0);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(b >> 32), 0);
+  return __longlong_as_double((int64_t)(((uint64_t)hi << 32) | lo));
+}
+
 // Exactly rounded sum of v[0..TT) over the 64 lanes of a wavefront; every lane
-// gets the same value. scr: this wavefront's LDS scratch of at least kAccLimbs
-// doubles, used only when the compensated sum is neither exact nor certified.
+// gets the same value. The merges may run in any order: the result is the
+// exactly rounded sum either way. scr: this wavefront's LDS scratch of at least
+// kAccLimbs doubles, used only when the compensated sum is neither exact nor
+// certified. Every lane must be active.
 template <int TT>
 __device__ __forceinline__ double wave_sum_exact(const double (&v)[TT], double *scr) {
   const int lane = threadIdx.x & (kWave - 1);
   XSum x{0.0, 0.0, 1};
 #pragma unroll
   for (int t = 0; t < TT; ++t) x = xsum_add(x, v[t]);
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-    x = xsum_merge(x, XSum{__shfl_xor(x.s, off), __shfl_xor(x.c, off), __shfl_xor(x.exact, off)});
-  x = XSum{__shfl(x.s, 0), __shfl(x.c, 0), __shfl(x.exact, 0)};
+  x = xsum_step<1>(x);
+  x = xsum_step<2>(x);
+  x = xsum_step<4>(x);
+  x = xsum_step<8>(x);
+  x = xsum_step<16>(x);
+  x = xsum_step<32>(x);
+  x = XSum{lane0(x.s), lane0(x.c), __builtin_amdgcn_readlane(x.exact, 0)};
   double r;
   if (x.exact && isfinite(x.s)) return x.s + x.c;
   if (certified_round(x.s, x.c, (int64_t)kWave * TT, r)) return r;
