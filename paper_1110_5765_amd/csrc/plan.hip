@@ -239,6 +239,28 @@ struct PlanArgs {
 
 __device__ __forceinline__ int srow(int W) { return W - 2; }   // s table row of W
 
+// The largest d over the wavefront, the lowest l among equals, and the value w
+// that comes with it; every lane gets the result. A maximum under this total
+// order does not depend on the order of the merges, so the steps run as in
+// wave_sum_exact (four DPP moves, two ds_bpermute exchanges). l = INT64_MAX
+// marks a lane without a candidate. Every lane must be active.
+template <int OFF>
+__device__ __forceinline__ void argmax_step(double &d, int &l, int &w) {
+  const double od = lane_partner<OFF>(d);
+  const int ol = lane_partner<OFF>(l), ow = lane_partner<OFF>(w);
+  if (od > d || (od == d && ol < l)) { d = od; l = ol; w = ow; }
+}
+__device__ __forceinline__ void wave_argmax(double &d, int64_t &l64, int &w) {
+  int l = l64 == INT64_MAX ? INT_MAX : (int)l64;     // l < 2^31 (at most 512 subblocks)
+  argmax_step<1>(d, l, w);
+  argmax_step<2>(d, l, w);
+  argmax_step<4>(d, l, w);
+  argmax_step<8>(d, l, w);
+  argmax_step<16>(d, l, w);
+  argmax_step<32>(d, l, w);
+  l64 = l == INT_MAX ? INT64_MAX : (int64_t)l;
+}
+
 // TT: subblocks per lane the kernel is compiled for (T = ceil(nL / 64) <= TT).
 template <int TT>
 __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
@@ -385,13 +407,7 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
           if (level[t] == v) { dv = dopt[v][t]; wc = a.w_desc[v]; wn = a.w_desc[v + 1 < kMaxOpt ? v + 1 : v]; }
         if (dv > bd || (dv == bd && l < bl)) { bd = dv; bl = l; bdelta = a.units[wc] - a.units[wn]; }
       }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double od = __shfl_xor(bd, off);
-        const int64_t ol = __shfl_xor(bl, off);
-        const int odl = __shfl_xor(bdelta, off);
-        if (od > bd || (od == bd && ol < bl)) { bd = od; bl = ol; bdelta = odl; }
-      }
+      wave_argmax(bd, bl, bdelta);
       if (bl == INT64_MAX || !(bd > 0.0)) break;
       if (bd < kDUnavailable && (double)(saved - bdelta) < target) break;
       saved -= bdelta;
@@ -514,12 +530,8 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
           for (int v = 0; v < kMaxOpt; ++v) if (level[t] == v) dv = dopt[v][t];
           if (dv > bd || (dv == bd && l < bl)) { bd = dv; bl = l; }
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          double od = __shfl_xor(bd, off);
-          int64_t ol = __shfl_xor(bl, off);
-          if (od > bd || (od == bd && ol < bl)) { bd = od; bl = ol; }
-        }
+        int unused = 0;
+        wave_argmax(bd, bl, unused);
         if (bl == INT64_MAX) break;               // everything already at the lowest W
         // within the budget, and no unavailable option left (they are the largest D)
         if (!(total > budget) && bd < kDUnavailable) break;
