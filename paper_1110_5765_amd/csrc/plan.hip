@@ -261,14 +261,37 @@ __device__ __forceinline__ void wave_argmax(double &d, int64_t &l64, int &w) {
   l64 = l == INT_MAX ? INT64_MAX : (int64_t)l;
 }
 
+// Lane k's value of v, for k uniform over the wavefront.
+__device__ __forceinline__ int64_t lane_at(int64_t v, int k) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, k);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), k);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Order key of a double that is not negative and not NaN: its bits with the
+// sign cleared (so -0 keys as +0). Keys compare as integers exactly as the
+// values compare as numbers, +inf included.
+__device__ __forceinline__ int64_t order_key(double d) { return __double_as_longlong(d) & INT64_MAX; }
+
+// Sum over the wavefront in plain double arithmetic (not exactly rounded; the
+// value of lane 0 for every lane). Every lane must be active.
+__device__ __forceinline__ double wave_sum_fast(double s) {
+  s += lane_partner<1>(s);
+  s += lane_partner<2>(s);
+  s += lane_partner<4>(s);
+  s += lane_partner<8>(s);
+  s += lane_partner<16>(s);
+  s += lane_partner<32>(s);
+  return lane0(s);
+}
+
 // TT: subblocks per lane the kernel is compiled for (T = ceil(nL / 64) <= TT).
 template <int TT>
 __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
-  constexpr int kEnt = (kMaxOpt - 1) * TT * kWave;   // entry slots per wavefront
   __shared__ float sh_fr[3][kMaxR], sh_fs2[3][kMaxR];
   __shared__ short sh_idx[3][kMaxR];
   __shared__ int sh_cnt[3];
-  __shared__ double sh_ent[kThreads / kWave][kEnt];
+  __shared__ double sh_scr[kThreads / kWave][kAccLimbs];
   // options over the calibrated grid: distortion (SNR) and throughput (ACCEL) control
   const bool snr = a.ctrl == TDGEMM_CTRL_SNR || a.ctrl == TDGEMM_CTRL_ACCEL;
   if (snr) {
@@ -295,8 +318,8 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
   int kopt[kMaxOpt][TT];
   int level[TT];
   double sigv[TT];                                // signal terms of the Sec. 6 budget
-  // this wavefront's LDS: the entries of the bisection, or the terms of an exact sum
-  double *scr = sh_ent[threadIdx.x / kWave];
+  // this wavefront's LDS for the long accumulator of an exact sum
+  double *scr = sh_scr[threadIdx.x / kWave];
   // With one subblock per lane (nL <= 64), LP lanes share each subblock's
   // table scans (the plan is latency-bound and the scans are its longest
   // chains): subblock l is computed by lanes l LP .. l LP + LP - 1 and its
@@ -372,54 +395,24 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
     }
     return wave_sum_exact<TT>(dvs, scr);
   };
+  auto total_fast = [&](const int (&rank)[kMaxOpt - 1][TT], int cut) {
+    double sum = 0.0;
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+      int lv = 0;
+#pragma unroll
+      for (int v = 0; v < kMaxOpt - 1; ++v) lv += (rank[v][t] < cut) ? 1 : 0;
+#pragma unroll
+      for (int v = 0; v < kMaxOpt; ++v) if (lv == v) sum += dopt[v][t];
+    }
+    return wave_sum_fast(sum);
+  };
 
   double budget = 0.0;
   const int n_ent = a.n_opt - 1;                  // entry levels 0 .. n_opt - 2
-  if (a.ctrl == TDGEMM_CTRL_ACCEL && n_ent > 0) {
-    // Throughput constraint: the pair with the largest current D (lowest l among
-    // equals) drops one level while the inner kernel keeps saving at least
-    // accel * nL * units[W_max] and that D is positive. units[W] is the work a
-    // pair saves at W in integers: twelfths of a W = 1 product, 12 - 12 / W, or
-    // units of measured time from the accelerations F_W (Sec. 5.B). An
-    // unavailable option (D >= kDUnavailable) drops whatever the constraint:
-    // its product cannot be formed.
-    int own = 0;
-#pragma unroll
-    for (int t = 0; t < TT; ++t)
-      if (t < T && lane + (int64_t)kWave * t < pb.nL) own += a.units[a.w_desc[0]];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) own += __shfl_xor(own, off);
-    int saved = own;
-    const double frac = a.tile ? a.tile[i * pb.nJ + j] : a.accel;
-    const double target = (frac * (double)pb.nL) * (double)a.units[a.w_desc[0]];
-    for (;;) {
-      double bd = -INFINITY;
-      int64_t bl = INT64_MAX;
-      int bdelta = 0;
-#pragma unroll
-      for (int t = 0; t < TT; ++t) {
-        const int64_t l = lane + (int64_t)kWave * t;
-        if (t >= T || l >= pb.nL || level[t] >= a.n_opt - 1) continue;
-        double dv = 0.0;
-        int wc = 1, wn = 1;
-#pragma unroll
-        for (int v = 0; v < kMaxOpt; ++v)
-          if (level[t] == v) { dv = dopt[v][t]; wc = a.w_desc[v]; wn = a.w_desc[v + 1 < kMaxOpt ? v + 1 : v]; }
-        if (dv > bd || (dv == bd && l < bl)) { bd = dv; bl = l; bdelta = a.units[wc] - a.units[wn]; }
-      }
-      wave_argmax(bd, bl, bdelta);
-      if (bl == INT64_MAX || !(bd > 0.0)) break;
-      if (bd < kDUnavailable && (double)(saved - bdelta) < target) break;
-      saved -= bdelta;
-      if ((bl & (kWave - 1)) == lane) {
-        const int tt = (int)(bl / kWave);
-#pragma unroll
-        for (int t = 0; t < TT; ++t) if (t == tt) level[t] += 1;
-      }
-    }
-  } else if (a.ctrl == TDGEMM_CTRL_SNR && n_ent > 0) {
-    budget = (a.tile ? a.tile[i * pb.nJ + j] : a.snr_lin) * wave_sum_exact<TT>(sigv, scr);
-    // does every pair's D decrease strictly along its entries (and weakly to the floor)?
+
+  // does every pair's D decrease strictly along its entries (and weakly to the floor)?
+  auto monotone = [&]() {
     bool mono = true;
 #pragma unroll
     for (int t = 0; t < TT; ++t)
@@ -430,84 +423,202 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
         if (!(d1 <= d0)) mono = false;
         if (v + 1 < n_ent && d1 > 0.0 && !(d0 > d1)) mono = false;
       }
-    if (__all(mono)) {
-      double *ent = sh_ent[threadIdx.x / kWave];
+    return __all(mono) != 0;
+  };
+
+  // Rank of each own entry with D > 0 among the entries of the inner kernel:
+  // the entries with a larger D, or an equal D and a lower l (only entries with
+  // D > 0 can be counted). The count runs over the n_ent levels in use, compiled
+  // for each count, and over the subblocks that exist (lanes beyond nL hold
+  // D = 0, which counts for no ranked entry), reading each entry from its lane.
+  // Entries that are not ranked get INT_MAX. n_pos: ranked entries; n_unav:
+  // those with D >= kDUnavailable, which rank first. Called only when the
+  // entries are monotone, hence not negative and not NaN (order_key).
+  int rank[kMaxOpt - 1][TT];
+  int n_pos = 0, n_unav = 0;
+  auto rank_entries = [&]() {
+    auto count_above = [&](auto nec) {
+      constexpr int NE = decltype(nec)::value;
+      // entry e counts slot s when key_s > key_e - [l_s < l_e], i.e. when
+      // key_e - key_s - [l_s < l_e] is negative: integer arithmetic only
+      int64_t ke[NE][TT];
+      int cnt[NE][TT];
 #pragma unroll
-      for (int v = 0; v < kMaxOpt - 1; ++v)
+      for (int v = 0; v < NE; ++v)
 #pragma unroll
-        for (int t = 0; t < TT; ++t)
-          if (v < n_ent && t < T) ent[(v * T + t) * kWave + lane] = dopt[v][t];
-      wave_sync_lds();
-      // rank of each own entry with D > 0: entries with a larger D, or equal D and
-      // lower l (only entries with D > 0 can be counted). The count runs over the
-      // n_ent levels in use, compiled for each count, with no test of validity
-      // inside the loop; entries that are not ranked get INT_MAX afterwards.
-      int rank[kMaxOpt - 1][TT];
-      const int nslot = n_ent * T * kWave;
-      auto count_above = [&](auto nec) {
-        constexpr int NE = decltype(nec)::value;
-        int cnt[NE][TT];
+        for (int t = 0; t < TT; ++t) { ke[v][t] = order_key(dopt[v][t]); cnt[v][t] = 0; }
 #pragma unroll
-        for (int v = 0; v < NE; ++v)
+      for (int vs = 0; vs < NE; ++vs)
 #pragma unroll
-          for (int t = 0; t < TT; ++t) cnt[v][t] = 0;
-#pragma unroll 4
-        for (int sidx = 0; sidx < nslot; ++sidx) {
-          const double ds = ent[sidx];
-          const int ls = ((sidx / kWave) % T) * kWave + (sidx & (kWave - 1));
+        for (int ts = 0; ts < TT; ++ts) {
+          if (ts >= T) continue;
+          const int nk = (int)min<int64_t>(kWave, pb.nL - (int64_t)ts * kWave);
+          const int64_t src = ke[vs][ts];
+          // slots k .. k + Q - 1 at a time: independent chains for the single
+          // wavefront of the SIMD
+          auto count_slots = [&](int k, auto qc) {
+            constexpr int Q = decltype(qc)::value;
+            int64_t ks[Q];
 #pragma unroll
-          for (int t = 0; t < TT; ++t) {
-            const bool lower = ls < t * kWave + lane;
+            for (int q = 0; q < Q; ++q) ks[q] = lane_at(src, k + q);   // entry (vs, subblock ts 64 + k + q)
 #pragma unroll
-            for (int v = 0; v < NE; ++v) {
-              const double de = dopt[v][t];
-              cnt[v][t] += (ds > de || (ds == de && lower)) ? 1 : 0;
-            }
-          }
+            for (int t = 0; t < TT; ++t)
+#pragma unroll
+              for (int v = 0; v < NE; ++v) {
+                int c = 0;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                  const int64_t lower = (int64_t)((uint32_t)(ts * kWave + k + q - (t * kWave + lane)) >> 31);
+                  c += (int)((uint64_t)(ke[v][t] - ks[q] - lower) >> 63);
+                }
+                cnt[v][t] += c;
+              }
+          };
+          int k = 0;
+#pragma unroll 1
+          for (; k + 4 <= nk; k += 4) count_slots(k, std::integral_constant<int, 4>{});
+#pragma unroll 1
+          for (; k < nk; ++k) count_slots(k, std::integral_constant<int, 1>{});
         }
-#pragma unroll
-        for (int v = 0; v < kMaxOpt - 1; ++v)
-#pragma unroll
-          for (int t = 0; t < TT; ++t) {
-            int c = 0;
-#pragma unroll
-            for (int u = 0; u < NE; ++u) if (u == v) c = cnt[u][t];
-            rank[v][t] = (v < n_ent && dopt[v][t] > 0.0) ? c : INT_MAX;
-          }
-      };
-      if (n_ent == 1)      count_above(std::integral_constant<int, 1>{});
-      else if (n_ent == 2) count_above(std::integral_constant<int, 2>{});
-      else                 count_above(std::integral_constant<int, 3>{});
-      // n_unav: entries with D >= kDUnavailable, ranked first; the greedy removes
-      // them whatever the budget
-      int n_pos = 0, n_unav = 0;
 #pragma unroll
       for (int v = 0; v < kMaxOpt - 1; ++v)
 #pragma unroll
         for (int t = 0; t < TT; ++t) {
-          n_pos += __popcll(__ballot(rank[v][t] != INT_MAX));
-          n_unav += __popcll(__ballot(rank[v][t] != INT_MAX && dopt[v][t] >= kDUnavailable));
+          int c = 0;
+#pragma unroll
+          for (int u = 0; u < NE; ++u) if (u == v) c = cnt[u][t];
+          rank[v][t] = (v < n_ent && dopt[v][t] > 0.0) ? c : INT_MAX;
         }
+    };
+    if (n_ent == 1)      count_above(std::integral_constant<int, 1>{});
+    else if (n_ent == 2) count_above(std::integral_constant<int, 2>{});
+    else                 count_above(std::integral_constant<int, 3>{});
+#pragma unroll
+    for (int v = 0; v < kMaxOpt - 1; ++v)
+#pragma unroll
+      for (int t = 0; t < TT; ++t) {
+        n_pos += __popcll(__ballot(rank[v][t] != INT_MAX));
+        n_unav += __popcll(__ballot(rank[v][t] != INT_MAX && dopt[v][t] >= kDUnavailable));
+      }
+  };
+  // levels after dropping every entry ranked below `cut` (INT_MAX: all)
+  auto levels_at = [&](int cut) {
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+      int lv = 0;
+#pragma unroll
+      for (int v = 0; v < kMaxOpt - 1; ++v)
+        lv += (v < n_ent && (cut == INT_MAX || rank[v][t] < cut)) ? 1 : 0;
+      level[t] = lv;
+    }
+  };
+
+  if (a.ctrl == TDGEMM_CTRL_ACCEL && n_ent > 0) {
+    // Throughput constraint: the pair with the largest current D (lowest l among
+    // equals) drops one level while the inner kernel keeps saving at least
+    // accel * nL * units[W_max] and that D is positive. units[W] is the work a
+    // pair saves at W in integers: twelfths of a W = 1 product, 12 - 12 / W, or
+    // units of measured time from the accelerations F_W (Sec. 5.B). An
+    // unavailable option (D >= kDUnavailable) drops whatever the constraint:
+    // its product cannot be formed.
+    int64_t own = 0;
+#pragma unroll
+    for (int t = 0; t < TT; ++t)
+      if (t < T && lane + (int64_t)kWave * t < pb.nL) own += a.units[a.w_desc[0]];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) own += __shfl_xor(own, off);
+    const double frac = a.tile ? a.tile[i * pb.nJ + j] : a.accel;
+    const double target = (frac * (double)pb.nL) * (double)a.units[a.w_desc[0]];
+    bool gains = false;                           // does some drop add saved work?
+#pragma unroll
+    for (int v = 0; v + 1 < kMaxOpt; ++v)
+      if (v < n_ent && a.units[a.w_desc[v]] < a.units[a.w_desc[v + 1]]) gains = true;
+    if (!gains && monotone()) {
+      // With D falling along every pair's entries, the greedy drops entries in
+      // rank order; with no drop adding saved work, the saving only falls along
+      // that order. The greedy therefore stops at the longest prefix of the
+      // ranking that keeps the saving at or above the target (the unavailable
+      // entries, ranked first, whatever it), found by bisection.
+      rank_entries();
+      auto saved_at = [&](int cut) {
+        int64_t s = 0;
+#pragma unroll
+        for (int v = 0; v + 1 < kMaxOpt; ++v)
+#pragma unroll
+          for (int t = 0; t < TT; ++t)
+            if (v < n_ent && rank[v][t] < cut) s += a.units[a.w_desc[v]] - a.units[a.w_desc[v + 1]];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        return own - s;
+      };
+      int lo = n_unav, hi = n_pos;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((double)saved_at(mid) >= target) lo = mid;
+        else hi = mid - 1;
+      }
+      levels_at(lo);
+    } else {
+      int64_t saved = own;
+      for (;;) {
+        double bd = -INFINITY;
+        int64_t bl = INT64_MAX;
+        int bdelta = 0;
+#pragma unroll
+        for (int t = 0; t < TT; ++t) {
+          const int64_t l = lane + (int64_t)kWave * t;
+          if (t >= T || l >= pb.nL || level[t] >= a.n_opt - 1) continue;
+          double dv = 0.0;
+          int wc = 1, wn = 1;
+#pragma unroll
+          for (int v = 0; v < kMaxOpt; ++v)
+            if (level[t] == v) { dv = dopt[v][t]; wc = a.w_desc[v]; wn = a.w_desc[v + 1 < kMaxOpt ? v + 1 : v]; }
+          if (dv > bd || (dv == bd && l < bl)) { bd = dv; bl = l; bdelta = a.units[wc] - a.units[wn]; }
+        }
+        wave_argmax(bd, bl, bdelta);
+        if (bl == INT64_MAX || !(bd > 0.0)) break;
+        if (bd < kDUnavailable && (double)(saved - bdelta) < target) break;
+        saved -= bdelta;
+        if ((bl & (kWave - 1)) == lane) {
+          const int tt = (int)(bl / kWave);
+#pragma unroll
+          for (int t = 0; t < TT; ++t) if (t == tt) level[t] += 1;
+        }
+      }
+    }
+  } else if (a.ctrl == TDGEMM_CTRL_SNR && n_ent > 0) {
+    budget = (a.tile ? a.tile[i * pb.nJ + j] : a.snr_lin) * wave_sum_exact<TT>(sigv, scr);
+    if (monotone()) {
+      rank_entries();
       int cut;
       if (!(total_at(rank, n_pos) <= budget)) {
         cut = INT_MAX;                            // the greedy empties every entry
       } else {
+        // The exact total falls with the cut, so the cut is the smallest one
+        // whose exact total is within the budget. A bisection over plain sums
+        // proposes it, and two exact totals confirm it (the proposal within the
+        // budget, its predecessor not); otherwise the bisection runs again over
+        // exact totals.
         int lo = n_unav, hi = n_pos;
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
-          if (total_at(rank, mid) <= budget) hi = mid;
+          if (total_fast(rank, mid) <= budget) hi = mid;
           else lo = mid + 1;
+        }
+        const bool found = (lo == n_pos || total_at(rank, lo) <= budget) &&
+                           (lo == n_unav || !(total_at(rank, lo - 1) <= budget));
+        if (!found) {
+          lo = n_unav;
+          hi = n_pos;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (total_at(rank, mid) <= budget) hi = mid;
+            else lo = mid + 1;
+          }
         }
         cut = lo;
       }
-#pragma unroll
-      for (int t = 0; t < TT; ++t) {
-        int lv = 0;
-#pragma unroll
-        for (int v = 0; v < kMaxOpt - 1; ++v)
-          lv += (v < n_ent && (cut == INT_MAX || rank[v][t] < cut)) ? 1 : 0;
-        level[t] = lv;
-      }
+      levels_at(cut);
     } else {
       for (;;) {
         double dvs[TT];

@@ -99,27 +99,28 @@ def test_plan_parity(td, case):
 
 
 ACCEL_CASES = [
-    # name, M, K, N, L, form, frac, w_allowed, inputs
-    ("accel_w2_f0", 128, 384, 128, 64, "sym", 0.0, (1, 2), "laplace"),
-    ("accel_w2_f03", 192, 640, 128, 64, "sym", 0.3, (1, 2), "gauss"),
-    ("accel_w2_f05_asym", 128, 512, 192, 64, "asym", 0.5, (1, 2), "laplace"),
-    ("accel_w2_f1", 128, 384, 128, 64, "sym", 1.0, (1, 2), "gauss"),
-    ("accel_w24_f06", 256, 1024, 64, 64, "sym", 0.6, (1, 2, 4), "laplace"),
-    ("accel_L128_many_l", 128, 128 * 70, 128, 128, "sym", 0.45, (1, 2, 4), "gauss"),
-    ("accel_ties", 128, 384, 128, 64, "sym", 0.5, (1, 2), "tiled"),
-    ("accel_L96_w23", 192, 96 * 20, 96, 96, "sym", 0.55, (1, 2, 3), "laplace"),
-    ("accel_L96_asym", 96, 96 * 12, 192, 96, "asym", 0.3, (1, 2, 3), "gauss"),
-    ("accel_L96_w1234", 192, 96 * 20, 96, 96, "sym", 0.6, (1, 2, 3, 4), "laplace"),
+    # name, M, K, N, L, form, frac, w_allowed, inputs, calib
+    ("accel_w2_f0", 128, 384, 128, 64, "sym", 0.0, (1, 2), "laplace", "std"),
+    ("accel_w2_f03", 192, 640, 128, 64, "sym", 0.3, (1, 2), "gauss", "std"),
+    ("accel_w2_f05_asym", 128, 512, 192, 64, "asym", 0.5, (1, 2), "laplace", "std"),
+    ("accel_w2_f1", 128, 384, 128, 64, "sym", 1.0, (1, 2), "gauss", "std"),
+    ("accel_w24_f06", 256, 1024, 64, 64, "sym", 0.6, (1, 2, 4), "laplace", "std"),
+    ("accel_L128_many_l", 128, 128 * 70, 128, 128, "sym", 0.45, (1, 2, 4), "gauss", "std"),
+    ("accel_ties", 128, 384, 128, 64, "sym", 0.5, (1, 2), "tiled", "std"),
+    ("accel_L96_w23", 192, 96 * 20, 96, 96, "sym", 0.55, (1, 2, 3), "laplace", "std"),
+    ("accel_L96_asym", 96, 96 * 12, 192, 96, "asym", 0.3, (1, 2, 3), "gauss", "std"),
+    ("accel_L96_w1234", 192, 96 * 20, 96, 96, "sym", 0.6, (1, 2, 3, 4), "laplace", "std"),
+    ("accel_nonmono_fallback", 192, 640, 128, 64, "sym", 0.5, (1, 2, 4), "gauss", "scaled_w4"),
 ]
 
 
 @pytest.mark.parametrize("case", ACCEL_CASES, ids=[c[0] for c in ACCEL_CASES])
 def test_accel_plan_parity(td, case):
     """Throughput-constrained pruning (F_kernel): records bit-exact to the oracle."""
-    name, M, K, N, L, form, frac, wal, kind = case
-    log(f"[plan] {name}: M={M} K={K} N={N} L={L} {form} F={frac} W={wal}")
+    name, M, K, N, L, form, frac, wal, kind, ck = case
+    log(f"[plan] {name}: M={M} K={K} N={N} L={L} {form} F={frac} W={wal} calib {ck}")
     A, B = _inputs(kind, M, K, N, zlib.crc32(name.encode()))
-    tabs = _calib("std", L, form)
+    tabs = _calib(ck, L, form)
     cfg = pl.Config(L=L, form=form, prec="f64", ctrl="accel", accel=frac, w_allowed=tuple(wal))
     ref = pl.make_plan(A, B, cfg, calib=tabs)
     calib = td.DeviceCalib(tabs[2].r, {W: t.s for W, t in tabs.items()})
