@@ -218,7 +218,10 @@ __global__ __launch_bounds__(kThreads) void k_stats(StatsArgs a) {
 // they come earlier in that order anyway. The sum after t removals is then
 // non-increasing in t, and the greedy's stopping point -- the first t whose
 // exactly rounded sum is within the budget -- is found by bisection over t
-// from the entries' ranks. Otherwise the greedy runs step by step.
+// from the entries' ranks. Under the throughput constraint the same order
+// holds, and while no drop adds saved work the stopping point -- the last t
+// that keeps the saving at the target -- is found the same way. Otherwise the
+// greedy runs step by step.
 constexpr int kMaxT = 8;          // up to 512 subblocks along K
 constexpr int kMaxOpt = 4;        // allowed W levels: at most {4, 3, 2, 1} (L = 96)
 
