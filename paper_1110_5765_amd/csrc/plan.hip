@@ -565,7 +565,7 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
       int lo = n_unav, hi = n_pos;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if ((double)saved_at(mid) >= target) lo = mid;
+        if (!((double)saved_at(mid) < target)) lo = mid;   // the greedy's test, NaN included
         else hi = mid - 1;
       }
       levels_at(lo);
@@ -601,8 +601,11 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
     budget = (a.tile ? a.tile[i * pb.nJ + j] : a.snr_lin) * wave_sum_exact<TT>(sigv, scr);
     if (monotone()) {
       rank_entries();
+      // the greedy's test for stopping: the sum does not exceed the budget (so
+      // that a NaN budget stops it at once, as it stops the step-by-step greedy)
+      auto within = [&](double total) { return !(total > budget); };
       int cut;
-      if (!(total_at(rank, n_pos) <= budget)) {
+      if (!within(total_at(rank, n_pos))) {
         cut = INT_MAX;                            // the greedy empties every entry
       } else {
         // The exact total falls with the cut, so the cut is the smallest one
@@ -613,17 +616,17 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
         int lo = n_unav, hi = n_pos;
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
-          if (total_fast(rank, mid) <= budget) hi = mid;
+          if (within(total_fast(rank, mid))) hi = mid;
           else lo = mid + 1;
         }
-        const bool found = (lo == n_pos || total_at(rank, lo) <= budget) &&
-                           (lo == n_unav || !(total_at(rank, lo - 1) <= budget));
+        const bool found = (lo == n_pos || within(total_at(rank, lo))) &&
+                           (lo == n_unav || !within(total_at(rank, lo - 1)));
         if (!found) {
           lo = n_unav;
           hi = n_pos;
           while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            if (total_at(rank, mid) <= budget) hi = mid;
+            if (within(total_at(rank, mid))) hi = mid;
             else lo = mid + 1;
           }
         }

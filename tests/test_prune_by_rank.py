@@ -60,13 +60,16 @@ def prune_by_rank(options, w_desc, d_kernel):
         lv = _levels(options, ent, cut)
         return exact_sum(options[l][w_desc[lv[l]]].d for l in range(len(options)))
 
-    if not total(n_pos) <= d_kernel:
+    def within(x):                     # the greedy's stopping test
+        return not x > d_kernel
+
+    if not within(total(n_pos)):
         level = [len(w_desc) - 1] * len(options)
     else:
         lo, hi = n_unav, n_pos
         while lo < hi:
             mid = (lo + hi) // 2
-            if total(mid) <= d_kernel:
+            if within(total(mid)):
                 hi = mid
             else:
                 lo = mid + 1
@@ -91,7 +94,7 @@ def prune_accel_by_rank(options, w_desc, frac, units=None):
     lo, hi = n_unav, n_pos
     while lo < hi:
         mid = (lo + hi + 1) // 2
-        if float(saved(mid)) >= target:
+        if not float(saved(mid)) < target:
             lo = mid
         else:
             hi = mid - 1
@@ -135,6 +138,18 @@ def test_snr_prune_by_rank_equals_greedy(kern, k, shift):
     if shift:
         b = b * (1.0 + shift * 2.0 ** -52) if b > 0.0 else (2.0 ** -1074 if shift > 0 else 0.0)
     assert prune_by_rank(options, w_desc, b) == ct.prune(options, w_desc, b)
+
+
+@settings(max_examples=100, deadline=None)
+@given(inner_kernel())
+def test_nan_budget_and_target_stop_like_the_greedy(kern):
+    """A NaN budget stops the greedy at once (after the unavailable options), and
+    a NaN throughput target never stops it: the bisections take the greedy's own
+    comparisons, so they agree there too."""
+    w_desc, options = kern
+    nan = float("nan")
+    assert prune_by_rank(options, w_desc, nan) == ct.prune(options, w_desc, nan)
+    assert prune_accel_by_rank(options, w_desc, nan) == ct.prune_accel(options, w_desc, nan)
 
 
 @settings(max_examples=400, deadline=None)
