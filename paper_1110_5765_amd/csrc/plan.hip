@@ -94,8 +94,45 @@ __device__ __forceinline__ void block_stats(const T *__restrict__ X, int64_t ld,
   __syncthreads();
   if (!s_certified) {
     // The sum lies too close to a rounding boundary for the compensated pair to
-    // decide: every square, split exactly into its rounded value and error, goes
-    // into an exact long accumulator in LDS, then one thread rounds it once.
+    // decide (an exact tie, say, which data of few significant bits make
+    // common). A second pass sums the squares, split exactly into their rounded
+    // values and errors, as compensated pairs that record whether every
+    // addition into the correction was exact; if so, the pair holds the exact
+    // sum and one rounding gives it.
+    XSum x{0.0, 0.0, 1};
+    for (int e = tid; e < L * L; e += kThreads) {
+      const int r = e / L, c = e - (e / L) * L;
+      if (r < vr && c < vc) {
+        const double v = (double)X[(int64_t)r * ld + c];
+        const double p = v * v;
+        x = xsum_add(xsum_add(x, p), __builtin_fma(v, v, -p));
+      }
+    }
+    x = xsum_step<1>(x);
+    x = xsum_step<2>(x);
+    x = xsum_step<4>(x);
+    x = xsum_step<8>(x);
+    x = xsum_step<16>(x);
+    x = xsum_step<32>(x);
+    __shared__ double s_xs[kThreads / kWave], s_xc[kThreads / kWave];
+    __shared__ int s_xe[kThreads / kWave];
+    if ((tid & (kWave - 1)) == 0) {
+      s_xs[tid / kWave] = x.s;
+      s_xc[tid / kWave] = x.c;
+      s_xe[tid / kWave] = x.exact;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      XSum t{s_xs[0], s_xc[0], s_xe[0]};
+      for (int q = 1; q < kThreads / kWave; ++q) t = xsum_merge(t, XSum{s_xs[q], s_xc[q], s_xe[q]});
+      s_certified = (t.exact && isfinite(t.s)) ? 1 : 0;
+      if (s_certified) s_sum = t.s + t.c;
+    }
+    __syncthreads();
+  }
+  if (!s_certified) {
+    // Otherwise every square and its error go into an exact long accumulator
+    // in LDS, and one thread rounds it once.
     __shared__ int64_t s_acc[kAccLimbs];
     for (int k = tid; k < kAccLimbs; k += kThreads) s_acc[k] = 0;
     __syncthreads();
