@@ -257,7 +257,9 @@ def test_sums_at_rounding_boundaries(td):
     rounds up; block (0, 1) holds 1, 2^-27, 2^-27 (an exact tie, to even: 1).
     The single inner kernel's signal terms L s_a^2 s_b^2 are 1, 2^-54, 2^-54,
     2^-200 (one nonzero element per block of A row 1 and B column 1), whose sum
-    rounds up too. A compensated sum rounded once gives 1 in both cases."""
+    rounds up too. A compensated sum rounded once gives 1 in both cases. Block
+    (0, 1) is settled by the exact compensated pair (every addition into the
+    correction is exact), block (0, 0) only by the long accumulator."""
     L, M, K, N = 64, 128, 4 * 64, 128
     rng = np.random.default_rng(2024)
     A = rng.standard_normal((M, K))
