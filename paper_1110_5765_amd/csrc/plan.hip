@@ -333,6 +333,59 @@ __device__ __forceinline__ double wave_sum_fast(double s) {
   return lane0(s);
 }
 
+// argmin_nsr (with LP = 1) for the TT subblocks of a lane at once; act[t]:
+// subblock t exists and its pair has nonzero ranges. One pass over the table
+// serves all of them, so their chains interleave; each result equals
+// argmin_nsr's (the same FP32 threshold, then the first exact minimum in
+// ascending order).
+template <int TT>
+__device__ __forceinline__ void argmin_nsr_lanes(const double (&L_eff)[TT], const BlockMoments (&a)[TT],
+                                                 const BlockMoments (&b)[TT], const bool (&act)[TT],
+                                                 const double *r, const double *s, const short *idx,
+                                                 const float *fr, const float *fs2, int cnt, int (&kout)[TT]) {
+  double ss[TT];
+  float x0[TT], invL[TT], best[TT], thr[TT];
+#pragma unroll
+  for (int t = 0; t < TT; ++t) {
+    ss[t] = a[t].sigma * b[t].sigma;
+    x0[t] = act[t] ? (float)(((L_eff[t] * a[t].amax) * b[t].amax) / ss[t]) : 0.0f;
+    invL[t] = act[t] ? 1.0f / (float)L_eff[t] : 0.0f;
+    best[t] = INFINITY;
+  }
+#pragma unroll 2
+  for (int i = 0; i < cnt; ++i) {
+    const float f = fr[i], g = fs2[i];
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+      const float x = x0[t] * f;
+      best[t] = fminf(best[t], x * ((1.0f / 6.0f) + x * ((1.0f / 144.0f) + g * invL[t])));
+    }
+  }
+  int kbest[TT];
+  double vbest[TT];
+#pragma unroll
+  for (int t = 0; t < TT; ++t) {
+    thr[t] = !act[t] ? -INFINITY : (best[t] < INFINITY) ? best[t] * (1.0f + 1e-5f) : INFINITY;
+    kbest[t] = -1;
+    vbest[t] = INFINITY;
+  }
+  for (int i = 0; i < cnt; ++i) {
+    const float f = fr[i], g = fs2[i];
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+      const float x = x0[t] * f;
+      const float v = x * ((1.0f / 6.0f) + x * ((1.0f / 144.0f) + g * invL[t]));
+      if (v <= thr[t]) {
+        const int k = idx[i];
+        const double e = nsr_exact(L_eff[t], a[t].amax, b[t].amax, ss[t], r[k], s[k]);
+        if (e < vbest[t]) { vbest[t] = e; kbest[t] = k; }
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < TT; ++t) kout[t] = kbest[t];
+}
+
 // TT: subblocks per lane the kernel is compiled for (T = ceil(nL / 64) <= TT).
 template <int TT>
 __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
@@ -389,6 +442,45 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
     const BlockMoments mb = moments(a.stats_b[l * pb.nJ + j]);
     sigv[t] = (L_eff * (ma.sigma * ma.sigma)) * (mb.sigma * mb.sigma);
   }
+  if constexpr (TT != 1 && TT != kMaxT) {
+    // several subblocks per lane: their table scans run together
+    if (snr) {
+      double Le[TT];
+      BlockMoments ma[TT], mb[TT];
+      bool act[TT];
+#pragma unroll
+      for (int t = 0; t < TT; ++t) {
+        act[t] = false;
+        Le[t] = 1.0;
+        ma[t] = BlockMoments{0.0, 1.0};
+        mb[t] = BlockMoments{0.0, 1.0};
+        const int64_t l = lane + (int64_t)kWave * t;
+        if (t >= T || l >= pb.nL) continue;
+        Le[t] = (double)min<int64_t>(pb.L, pb.K - l * pb.L);
+        ma[t] = moments(a.stats_a[i * pb.nL + l]);
+        mb[t] = moments(a.stats_b[l * pb.nJ + j]);
+        act[t] = ma[t].amax != 0.0 && mb[t].amax != 0.0;   // else D = 0
+      }
+#pragma unroll 1
+      for (int v = 0; v < a.n_opt; ++v) {
+        const int W = a.w_desc[v];
+        if (W == 1) continue;                     // D = 0
+        const int q = srow(W);
+        const double *s = a.calib_s + q * a.n_r;
+        int k[TT];
+        argmin_nsr_lanes<TT>(Le, ma, mb, act, a.calib_r, s, sh_idx[q], sh_fr[q], sh_fs2[q], sh_cnt[q], k);
+#pragma unroll
+        for (int t = 0; t < TT; ++t) {
+          if (!act[t]) continue;
+          const double d = (k[t] < 0) ? kDUnavailable
+                                      : option_at(W, Le[t], ma[t], mb[t], a.calib_r[k[t]], s[k[t]], a.u_safe).d;
+#pragma unroll
+          for (int u = 0; u < kMaxOpt; ++u)
+            if (u == v) { dopt[u][t] = d; kopt[u][t] = k[t]; }
+        }
+      }
+    }
+  } else {
 #pragma unroll
   for (int t = 0; t < TT; ++t) {
     if (t >= T) continue;
@@ -427,6 +519,7 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
       dopt[v][t] = own ? dv : 0.0;
       kopt[v][t] = own ? kv : -1;
     }
+  }
   }
 
   // level of slot t after removing every entry ranked below `cut`
