@@ -3,10 +3,13 @@
 Bar: block statistics and pair records bit-exact; byte operands bit-exact;
 INT8 per-pair products bit-exact (exact integers) and C bit-exact (the same
 float32 operations in the same order). FP8: the matrix cores of gfx950 do not
-round a 128-term sum of (exact) E4M3 products like IEEE float32 does; measured,
-each sum is within 2^-11.2 of its largest single product. The bar is 2^-10 of
-the largest product per output and 1e-4 relative (Frobenius) on C. The output
-SNR against the float64 product is logged for every case."""
+round a 128-term sum of (exact) E4M3 products like IEEE float32 does, and the
+order of their additions is not specified. The bar is the worst-case error of
+a float32 sum of n = 128 terms p_k with round-to-nearest in any order,
+gamma_(n-1) sum |p_k| <= 127 2^-24 128 max|p_k| < 2^-10 max|p_k|, per output;
+measured, each sum is within 2^-11.2 max|p_k|. On C the bar is 1e-4 relative
+(Frobenius). The output SNR against the float64 product is logged for every
+case."""
 import math
 import zlib
 
