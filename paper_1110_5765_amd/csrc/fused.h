@@ -749,14 +749,25 @@ __global__ __launch_bounds__(fused_threads<L>(), (L == 64 ? 2 : 1)) void k_fused
 }
 
 // C = sum over the groups g (ascending, from zero) of their partial results.
+// The partials are loaded eight groups at a time before they are added in
+// order, so that a thread has eight loads in flight (few threads, many groups).
 template <typename PT>
 __global__ __launch_bounds__(256) void k_sum_groups(const PT *__restrict__ part, int64_t ngroups,
                                                     int64_t M, int64_t N, PT *__restrict__ C,
                                                     int64_t ldc) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= M * N) return;
+  const int64_t mn = M * N;
+  if (e >= mn) return;
   PT total = (PT)0;
-  for (int64_t q = 0; q < ngroups; ++q) total = total + part[q * M * N + e];
+  int64_t q = 0;
+  for (; q + 8 <= ngroups; q += 8) {
+    PT v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(q + u) * mn + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) total = total + v[u];
+  }
+  for (; q < ngroups; ++q) total = total + part[q * mn + e];
   const int64_t r = e / N;
   C[r * ldc + (e - r * N)] = total;
 }
