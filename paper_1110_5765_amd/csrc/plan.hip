@@ -393,6 +393,15 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
   __shared__ short sh_idx[3][kMaxR];
   __shared__ int sh_cnt[3];
   __shared__ double sh_scr[kThreads / kWave][kAccLimbs];
+  // With two or four subblocks per lane a workgroup serves one inner kernel:
+  // its first wavefront plans it, and all four count the ranks of the pruning
+  // entries, a quarter of the slots each (the ranking is the longest chain).
+  constexpr bool kWide = TT > 1 && TT < kMaxT;
+  constexpr int kWaves = kThreads / kWave;
+  constexpr int kEnt = (kMaxOpt - 1) * TT * kWave;
+  __shared__ int64_t sh_keys[kWide ? kEnt : 1];
+  __shared__ int sh_part[kWide ? kWaves - 1 : 1][kWide ? kEnt : 1];
+  __shared__ int sh_need;
   // options over the calibrated grid: distortion (SNR) and throughput (ACCEL) control
   const bool snr = a.ctrl == TDGEMM_CTRL_SNR || a.ctrl == TDGEMM_CTRL_ACCEL;
   if (snr) {
@@ -408,9 +417,10 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
   }
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t tile = (int64_t)blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+  const int wv = threadIdx.x / kWave;
+  const int64_t tile = kWide ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * kWaves + wv;
   const Problem &pb = a.pb;
-  if (tile >= pb.nI * pb.nJ) return;
+  if (tile >= pb.nI * pb.nJ) return;              // the whole workgroup when kWide
   const int64_t i = tile / pb.nJ, j = tile - (tile / pb.nJ) * pb.nJ;
   const int T = (int)((pb.nL + kWave - 1) / kWave);
 
@@ -428,6 +438,7 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
   int LP = 1;
   if (TT == 1)
     while (LP < 16 && 2 * LP * pb.nL <= kWave) LP *= 2;
+  if (!kWide || wv == 0) {
 #pragma unroll
   for (int t = 0; t < TT; ++t) {
     level[t] = 0;
@@ -519,6 +530,7 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
       dopt[v][t] = own ? dv : 0.0;
       kopt[v][t] = own ? kv : -1;
     }
+  }
   }
   }
 
@@ -654,6 +666,119 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
     }
   };
 
+  // Does the pruning below rank its entries? D must fall along every pair's
+  // entries and, under the throughput constraint, no drop may add saved work.
+  bool need_rank = false;
+  if (!kWide || wv == 0) {
+    bool gains = false;
+#pragma unroll
+    for (int v = 0; v + 1 < kMaxOpt; ++v)
+      if (v < n_ent && a.units[a.w_desc[v]] < a.units[a.w_desc[v + 1]]) gains = true;
+    const bool ranked = a.ctrl == TDGEMM_CTRL_SNR || (a.ctrl == TDGEMM_CTRL_ACCEL && !gains);
+    need_rank = n_ent > 0 && ranked && monotone();
+  }
+  if constexpr (kWide) {
+    // The first wavefront's entries go to LDS (entry (v, t) of lane q at
+    // (v T + t) 64 + q); wavefront w counts the slot groups g = v T + t with
+    // g = w mod 4 for every entry, and the first wavefront adds the counts.
+    if (wv == 0) {
+      if (lane == 0) sh_need = need_rank ? 1 : 0;
+      if (need_rank) {
+#pragma unroll
+        for (int v = 0; v < kMaxOpt - 1; ++v)
+#pragma unroll
+          for (int t = 0; t < TT; ++t)
+            if (v < n_ent && t < T) sh_keys[(v * T + t) * kWave + lane] = order_key(dopt[v][t]);
+      }
+    }
+    __syncthreads();
+    const bool counting = sh_need != 0;
+    int cnt[kMaxOpt - 1][TT];
+#pragma unroll
+    for (int v = 0; v < kMaxOpt - 1; ++v)
+#pragma unroll
+      for (int t = 0; t < TT; ++t) cnt[v][t] = 0;
+    auto count_wide = [&](auto nec) {
+      constexpr int NE = decltype(nec)::value;
+      int64_t ke[NE][TT];
+      int c[NE][TT];
+#pragma unroll
+      for (int v = 0; v < NE; ++v)
+#pragma unroll
+        for (int t = 0; t < TT; ++t) {
+          ke[v][t] = t < T ? sh_keys[(v * T + t) * kWave + lane] : 0;
+          c[v][t] = 0;
+        }
+#pragma unroll 1
+      for (int g = wv; g < NE * T; g += kWaves) {
+        const int ts = g % T;
+        const int nk = (int)min<int64_t>(kWave, pb.nL - (int64_t)ts * kWave);
+        const int64_t *slot = sh_keys + g * kWave;
+        auto count_slots = [&](int k, auto qc) {
+          constexpr int Q = decltype(qc)::value;
+          int64_t ks[Q];
+#pragma unroll
+          for (int q = 0; q < Q; ++q) ks[q] = slot[k + q];
+#pragma unroll
+          for (int t = 0; t < TT; ++t)
+#pragma unroll
+            for (int v = 0; v < NE; ++v) {
+              int cc = 0;
+#pragma unroll
+              for (int q = 0; q < Q; ++q) {
+                const int64_t lower = (int64_t)((uint32_t)(ts * kWave + k + q - (t * kWave + lane)) >> 31);
+                cc += (int)((uint64_t)(ke[v][t] - ks[q] - lower) >> 63);
+              }
+              c[v][t] += cc;
+            }
+        };
+        int k = 0;
+#pragma unroll 1
+        for (; k + 4 <= nk; k += 4) count_slots(k, std::integral_constant<int, 4>{});
+#pragma unroll 1
+        for (; k < nk; ++k) count_slots(k, std::integral_constant<int, 1>{});
+      }
+#pragma unroll
+      for (int v = 0; v < NE; ++v)
+#pragma unroll
+        for (int t = 0; t < TT; ++t) cnt[v][t] = c[v][t];
+    };
+    if (counting) {
+      if (n_ent == 1)      count_wide(std::integral_constant<int, 1>{});
+      else if (n_ent == 2) count_wide(std::integral_constant<int, 2>{});
+      else                 count_wide(std::integral_constant<int, 3>{});
+      if (wv > 0) {
+#pragma unroll
+        for (int v = 0; v < kMaxOpt - 1; ++v)
+#pragma unroll
+          for (int t = 0; t < TT; ++t)
+            if (v < n_ent && t < T) sh_part[wv - 1][(v * T + t) * kWave + lane] = cnt[v][t];
+      }
+    }
+    __syncthreads();
+    if (wv != 0) return;
+    if (need_rank) {
+#pragma unroll
+      for (int v = 0; v < kMaxOpt - 1; ++v)
+#pragma unroll
+        for (int t = 0; t < TT; ++t) {
+          int total = cnt[v][t];
+          if (v < n_ent && t < T)
+            for (int w = 0; w < kWaves - 1; ++w) total += sh_part[w][(v * T + t) * kWave + lane];
+          rank[v][t] = (v < n_ent && dopt[v][t] > 0.0) ? total : INT_MAX;
+        }
+#pragma unroll
+      for (int v = 0; v < kMaxOpt - 1; ++v)
+#pragma unroll
+        for (int t = 0; t < TT; ++t) {
+          n_pos += __popcll(__ballot(rank[v][t] != INT_MAX));
+          n_unav += __popcll(__ballot(rank[v][t] != INT_MAX && dopt[v][t] >= kDUnavailable));
+        }
+    }
+  } else {
+    if (need_rank) rank_entries();
+  }
+
   if (a.ctrl == TDGEMM_CTRL_ACCEL && n_ent > 0) {
     // Throughput constraint: the pair with the largest current D (lowest l among
     // equals) drops one level while the inner kernel keeps saving at least
@@ -670,17 +795,12 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
     for (int off = 32; off > 0; off >>= 1) own += __shfl_xor(own, off);
     const double frac = a.tile ? a.tile[i * pb.nJ + j] : a.accel;
     const double target = (frac * (double)pb.nL) * (double)a.units[a.w_desc[0]];
-    bool gains = false;                           // does some drop add saved work?
-#pragma unroll
-    for (int v = 0; v + 1 < kMaxOpt; ++v)
-      if (v < n_ent && a.units[a.w_desc[v]] < a.units[a.w_desc[v + 1]]) gains = true;
-    if (!gains && monotone()) {
+    if (need_rank) {
       // With D falling along every pair's entries, the greedy drops entries in
       // rank order; with no drop adding saved work, the saving only falls along
       // that order. The greedy therefore stops at the longest prefix of the
       // ranking that keeps the saving at or above the target (the unavailable
       // entries, ranked first, whatever it), found by bisection.
-      rank_entries();
       auto saved_at = [&](int cut) {
         int64_t s = 0;
 #pragma unroll
@@ -729,8 +849,7 @@ __global__ __launch_bounds__(kThreads) void k_plan(PlanArgs a) {
     }
   } else if (a.ctrl == TDGEMM_CTRL_SNR && n_ent > 0) {
     budget = (a.tile ? a.tile[i * pb.nJ + j] : a.snr_lin) * wave_sum_exact<TT>(sigv, scr);
-    if (monotone()) {
-      rank_entries();
+    if (need_rank) {
       // the greedy's test for stopping: the sum does not exceed the budget (so
       // that a NaN budget stops it at once, as it stops the step-by-step greedy)
       auto within = [&](double total) { return !(total > budget); };
@@ -900,8 +1019,8 @@ hipError_t launch_plan(const PlanLaunch &p, hipStream_t st) {
   const unsigned blocks = (unsigned)((tiles + (kThreads / kWave) - 1) / (kThreads / kWave));
   const int64_t T = (p.pb.nL + kWave - 1) / kWave;
   if (T <= 1)      hipLaunchKernelGGL(k_plan<1>, dim3(blocks), dim3(kThreads), 0, st, a);
-  else if (T <= 2) hipLaunchKernelGGL(k_plan<2>, dim3(blocks), dim3(kThreads), 0, st, a);
-  else if (T <= 4) hipLaunchKernelGGL(k_plan<4>, dim3(blocks), dim3(kThreads), 0, st, a);
+  else if (T <= 2) hipLaunchKernelGGL(k_plan<2>, dim3((unsigned)tiles), dim3(kThreads), 0, st, a);   // one inner kernel per workgroup
+  else if (T <= 4) hipLaunchKernelGGL(k_plan<4>, dim3((unsigned)tiles), dim3(kThreads), 0, st, a);
   else             hipLaunchKernelGGL(k_plan<kMaxT>, dim3(blocks), dim3(kThreads), 0, st, a);
   return hipGetLastError();
 }
