@@ -196,17 +196,30 @@ def make_desc(A: torch.Tensor, B: torch.Tensor, *, L: int = 64, form: str = "sym
     return d
 
 
-def auto_k_split(M: int, N: int, K: int, L: int, prec: str = "f64", workgroups: int = 512) -> int:
-    """A k_split that gives about `workgroups` fused workgroups when M and N leave
-    fewer than 256 of them (one per CU); 1 otherwise. The fused kernel runs one
-    workgroup per inner kernel at every L and packing precision (`prec` is kept
-    for callers that name it). Only the order of the l-sum changes, in the way
+def auto_k_split(M: int, N: int, K: int, L: int, prec: str = "f64", cus: int = 256) -> int:
+    """A k_split for products whose M and N leave fewer fused workgroups than
+    CUs; 1 otherwise. With groups of g subblocks an inner kernel has
+    ceil(nL / g) groups, and the launch runs ceil(tiles * groups / slots) rounds
+    of workgroups that multiply g pairs each, where slots is the number of
+    fused workgroups resident at once (one per CU at L = 96 and 128; at L = 64
+    two for FP64 packing and three for FP32). A workgroup also costs about two
+    pairs' time of its own (first loads, writing its partial tile), so the
+    smallest rounds * (g + 2) wins, fewer groups on ties (less partial traffic
+    for the ordered group sum). Only the order of the l-sum changes, in the way
     tdgemm_desc.k_split describes."""
     nI, nJ, nL = -(-M // L), -(-N // L), -(-K // L)
     tiles = max(1, nI * nJ)
-    if nL <= 1 or tiles >= 256:
+    if nL <= 1 or tiles >= cus:
         return 1
-    return max(1, min(nL, -(-workgroups // tiles)))
+    slots = cus * ((3 if prec == "f32" else 2) if L == 64 else 1)
+    best = None
+    for g in range(1, nL + 1):
+        groups = -(-nL // g)
+        rounds = -(-(tiles * groups) // slots)
+        key = (rounds * (g + 2), groups)
+        if best is None or key < best[0]:
+            best = (key, groups)
+    return best[1]
 
 
 def torch_dtype(prec_code: int) -> torch.dtype:
