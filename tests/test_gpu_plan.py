@@ -53,6 +53,9 @@ CASES = [
     ("L96_many_l", 96, 96 * 70, 96, 96, "sym", 30.0, (1, 2, 3), "gauss", "std"),
     ("L96_asym_ragged", 64, 96 * 50 + 17, 70, 96, "asym", 25.0, (1, 2, 3), "laplace", "std"),
     ("L96_w1234_many_l", 96, 96 * 70, 96, 96, "sym", 22.0, (1, 2, 3, 4), "gauss", "std"),
+    # four subblocks per lane: one workgroup per inner kernel, four wavefronts ranking
+    ("T4_w124_ragged", 64, 64 * 200 + 5, 128, 64, "sym", 30.0, (1, 2, 4), "gauss", "std"),
+    ("T3_nonmono_fallback", 64, 64 * 150, 128, 64, "sym", 86.0, (1, 2, 4), "gauss", "scaled_w4"),
 ]
 
 
@@ -111,6 +114,7 @@ ACCEL_CASES = [
     ("accel_L96_asym", 96, 96 * 12, 192, 96, "asym", 0.3, (1, 2, 3), "gauss", "std"),
     ("accel_L96_w1234", 192, 96 * 20, 96, 96, "sym", 0.6, (1, 2, 3, 4), "laplace", "std"),
     ("accel_nonmono_fallback", 192, 640, 128, 64, "sym", 0.5, (1, 2, 4), "gauss", "scaled_w4"),
+    ("accel_T4_w124", 64, 64 * 230, 128, 64, "sym", 0.6, (1, 2, 4), "laplace", "std"),
 ]
 
 
