@@ -242,7 +242,8 @@ __global__ __launch_bounds__(kThreads) void k_stats(StatsArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Plan: one wavefront per inner kernel (i, j); lane q handles l = q + 64 t.
+// Plan: one wavefront per inner kernel (i, j); lane q handles l = q + 64 t (with
+// 65 to 256 subblocks, one workgroup per inner kernel, see kWide below).
 // For every allowed W > 1 it finds the option of Sec. 5.B (argmin of the eq. 27
 // noise over the calibrated grid), then prunes top-down (Sec. 6): while the
 // exactly rounded sum of the current D exceeds the budget, the pair with the
