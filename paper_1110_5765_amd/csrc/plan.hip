@@ -45,9 +45,22 @@ __device__ __forceinline__ void block_stats(const T *__restrict__ X, int64_t ld,
   constexpr int V = 16 / (int)sizeof(T);            // elements per 16-byte load
   constexpr int RV = L / V;                         // loads per row
   constexpr int NV = L * L / V / kThreads;          // loads per thread
+  // FP32 inputs: every square is exact in FP64, and the first pass already
+  // sums them as exact compensated pairs (below), so ties need no second pass
+  constexpr bool kX = std::is_same<T, float>::value;
   typedef T vec_t __attribute__((ext_vector_type(V)));
   const int tid = threadIdx.x;
   StatAcc acc0{INFINITY, -INFINITY, CSum{0.0, 0.0}}, acc1 = acc0;
+  XSum x0{0.0, 0.0, 1}, x1 = x0;
+  auto add = [&](StatAcc &acc, XSum &x, double v) {
+    if constexpr (kX) {
+      acc.mn = fmin(acc.mn, v);
+      acc.mx = fmax(acc.mx, v);
+      x = xsum_add(x, v * v);
+    } else {
+      stat_add(acc, v);
+    }
+  };
   const bool vec = vr == L && vc == L && ((uintptr_t)X % 16) == 0 &&
                    ((ld * (int64_t)sizeof(T)) % 16) == 0;
   if (vec) {
@@ -66,12 +79,15 @@ __device__ __forceinline__ void block_stats(const T *__restrict__ X, int64_t ld,
 #pragma unroll
       for (int q = 0; q < NH; ++q)
 #pragma unroll
-        for (int c = 0; c < V; ++c) stat_add((q & 1) ? acc1 : acc0, (double)v[q][c]);
+        for (int c = 0; c < V; ++c) {
+          if (q & 1) add(acc1, x1, (double)v[q][c]);
+          else       add(acc0, x0, (double)v[q][c]);
+        }
     }
   } else {
     for (int e = tid; e < L * L; e += kThreads) {
       const int r = e / L, c = e - (e / L) * L;
-      if (r < vr && c < vc) stat_add(acc0, (double)X[(int64_t)r * ld + c]);
+      if (r < vr && c < vc) add(acc0, x0, (double)X[(int64_t)r * ld + c]);
     }
   }
   StatAcc acc = stat_merge(acc0, acc1);
@@ -80,19 +96,52 @@ __device__ __forceinline__ void block_stats(const T *__restrict__ X, int64_t ld,
   __shared__ StatAcc s_w[kThreads / kWave];
   __shared__ double s_sum;
   __shared__ int s_certified;
+  __shared__ double s_xs[kThreads / kWave], s_xc[kThreads / kWave];
+  __shared__ int s_xe[kThreads / kWave];
+  // exact compensated pairs of the lanes, merged over the wavefront and then the
+  // workgroup; thread 0 gets the workgroup's pair
+  auto merge_x = [&](XSum x) {
+    x = xsum_step<1>(x);
+    x = xsum_step<2>(x);
+    x = xsum_step<4>(x);
+    x = xsum_step<8>(x);
+    x = xsum_step<16>(x);
+    x = xsum_step<32>(x);
+    if ((tid & (kWave - 1)) == 0) {
+      s_xs[tid / kWave] = x.s;
+      s_xc[tid / kWave] = x.c;
+      s_xe[tid / kWave] = x.exact;
+    }
+    __syncthreads();
+    XSum t{s_xs[0], s_xc[0], s_xe[0]};
+    for (int q = 1; q < kThreads / kWave; ++q) t = xsum_merge(t, XSum{s_xs[q], s_xc[q], s_xe[q]});
+    return t;
+  };
   if ((tid & (kWave - 1)) == 0) s_w[tid / kWave] = acc;
+  XSum tx{0.0, 0.0, 0};
+  if constexpr (kX) tx = merge_x(xsum_merge(x0, x1));
   __syncthreads();
   if (tid == 0) {
     StatAcc t = s_w[0];
     for (int q = 1; q < kThreads / kWave; ++q) t = stat_merge(t, s_w[q]);
     double r;
-    // 2 terms (rounded square and its error) per valid element
-    s_certified = certified_round(t.s.s, t.s.c, 2 * (int64_t)vr * vc, r) ? 1 : 0;
+    if constexpr (kX) {
+      // one exact term per valid element; the certificate covers inexact pairs
+      if (tx.exact && isfinite(tx.s)) {
+        s_certified = 1;
+        r = tx.s + tx.c;
+      } else {
+        s_certified = certified_round(tx.s, tx.c, (int64_t)vr * vc, r) ? 1 : 0;
+      }
+    } else {
+      // 2 terms (rounded square and its error) per valid element
+      s_certified = certified_round(t.s.s, t.s.c, 2 * (int64_t)vr * vc, r) ? 1 : 0;
+    }
     s_sum = r;
     s_w[0] = t;
   }
   __syncthreads();
-  if (!s_certified) {
+  if (!kX && !s_certified) {
     // The sum lies too close to a rounding boundary for the compensated pair to
     // decide (an exact tie, say, which data of few significant bits make
     // common). A second pass sums the squares, split exactly into their rounded
@@ -108,23 +157,8 @@ __device__ __forceinline__ void block_stats(const T *__restrict__ X, int64_t ld,
         x = xsum_add(xsum_add(x, p), __builtin_fma(v, v, -p));
       }
     }
-    x = xsum_step<1>(x);
-    x = xsum_step<2>(x);
-    x = xsum_step<4>(x);
-    x = xsum_step<8>(x);
-    x = xsum_step<16>(x);
-    x = xsum_step<32>(x);
-    __shared__ double s_xs[kThreads / kWave], s_xc[kThreads / kWave];
-    __shared__ int s_xe[kThreads / kWave];
-    if ((tid & (kWave - 1)) == 0) {
-      s_xs[tid / kWave] = x.s;
-      s_xc[tid / kWave] = x.c;
-      s_xe[tid / kWave] = x.exact;
-    }
-    __syncthreads();
+    const XSum t = merge_x(x);
     if (tid == 0) {
-      XSum t{s_xs[0], s_xc[0], s_xe[0]};
-      for (int q = 1; q < kThreads / kWave; ++q) t = xsum_merge(t, XSum{s_xs[q], s_xc[q], s_xe[q]});
       s_certified = (t.exact && isfinite(t.s)) ? 1 : 0;
       if (s_certified) s_sum = t.s + t.c;
     }

@@ -254,7 +254,8 @@ def test_plan_query_vs_oracle(td, case):
     log(f"[plan] query {name}: predicted SNR {got_snr:.3f} dB, W {got_hist.tolist()}, short {got_short}")
 
 
-def test_sums_at_rounding_boundaries(td):
+@pytest.mark.parametrize("dt", [np.float64, np.float32], ids=["f64", "f32"])
+def test_sums_at_rounding_boundaries(td, dt):
     """Exactly rounded sums by construction (statistics and the Sec. 6 budget).
     Block (0, 0) of A holds 1, 2^-27, 2^-27, 2^-100: its exact sum of squares
     1 + 2^-53 + 2^-200 lies just above the midpoint between 1 and 1 + 2^-52 and
@@ -263,7 +264,9 @@ def test_sums_at_rounding_boundaries(td):
     2^-200 (one nonzero element per block of A row 1 and B column 1), whose sum
     rounds up too. A compensated sum rounded once gives 1 in both cases. Block
     (0, 1) is settled by the exact compensated pair (every addition into the
-    correction is exact), block (0, 0) only by the long accumulator."""
+    correction is exact), block (0, 0) only by the long accumulator. Every value
+    is a float32 too: with float32 inputs the first pass sums the squares as
+    exact compensated pairs already."""
     L, M, K, N = 64, 128, 4 * 64, 128
     rng = np.random.default_rng(2024)
     A = rng.standard_normal((M, K))
@@ -279,6 +282,7 @@ def test_sums_at_rounding_boundaries(td):
     for l, (a, b) in enumerate(ab):
         A[64 + 3, l * 64 + 7] = a
         B[l * 64 + 11, 64 + 2] = b
+    A, B = A.astype(dt), B.astype(dt)
     tabs = _calib("std", L, "sym")
     cfg = oracle_cfg(L, "sym", "f64", "snr", 30.0, (1, 2), 2, 1.0, 127.0)
     ref = pl.make_plan(A, B, cfg, calib=tabs)
