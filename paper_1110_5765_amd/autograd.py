@@ -48,6 +48,7 @@ class TDContext:
         self.calib = calib
         self._ws: dict = {}
         self._prep: dict = {}
+        self._views: dict = {}
         self.calls = 0
         self.plain_calls = 0
         self.last_plan = None
@@ -85,15 +86,23 @@ class TDContext:
         return p
 
     def byte_operands(self, shapes: dict, device) -> tuple[torch.Tensor, torch.Tensor]:
-        """Cached byte operand buffers of the block-scaled forms (grown on demand)."""
+        """Cached byte operand buffers of the block-scaled forms (grown on demand),
+        and their views per operand shape (a training step asks for the same few)."""
+        vk = (device, shapes["qA"], shapes["qB"])
+        v = self._views.get(vk)
+        if v is not None:
+            return v
         key = ("bytes", device)
         need = shapes["qA"][0] * shapes["qA"][1] + shapes["qB"][0] * shapes["qB"][1]
         buf = self._ws.get(key)
         if buf is None or buf.numel() < need:
             buf = torch.empty(need, dtype=torch.uint8, device=device)
             self._ws[key] = buf
+            self._views = {}                      # views of the former buffer
         na = shapes["qA"][0] * shapes["qA"][1]
-        return buf[:na].view(shapes["qA"]), buf[na:need].view(shapes["qB"])
+        v = (buf[:na].view(shapes["qA"]), buf[na:need].view(shapes["qB"]))
+        self._views[vk] = v
+        return v
 
     def matmul(self, A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
         """A B through the library (A, B row-major or transposed views)."""
